@@ -1,0 +1,604 @@
+// polar_oracle.cpp -- plain CPU reference for polar codes and SC / SCS decoding.
+//
+// TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+// benchmark's CPU-baseline leg to check the HIP decoder.  The product library never
+// links or calls this code, and no source is shared between the two.
+//
+// Built with -O2, no fast-math and -ffp-contract=off, so binary32 arithmetic is plain
+// IEEE round-to-nearest-even with denormals, in program order.
+//
+// Paper: H. Aurora, W. Gross, "Towards Practical Software Stack Decoding of Polar
+// Codes".  Section numbers below refer to it.  Where the paper is silent or garbled the
+// reading taken is stated at the point of use (R-numbers match the list of readings in
+// the design notes).
+
+#include "polar_oracle.h"
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
+#include <vector>
+
+namespace {
+
+int log2_exact(int N) {
+  if (N < 2 || (N & (N - 1)) != 0) return -1;
+  int n = 0;
+  while ((1 << n) < N) ++n;
+  return n;
+}
+
+// ---------------------------------------------------------------------------------
+// Arithmetic of the LLR tree.  Section 2.2.1, eq. (minsum) and eq. (scest).
+//
+//   f(a, b)    = sign(a) sign(b) min(|a|, |b|)           (exact in every mode)
+//   g(a, b, u) = b + (-1)^u a                             (R1: the paper prints
+//                a + (-1)^u b, but its kernel figure feeds the XOR output into the
+//                first input, so the sign applies to the first operand; the literal
+//                formula fails noiseless decoding)
+//   HD(x)      = 1 iff x < 0                              (R2: -0 and +0 decide 0)
+//   PM update  : eq. (PMupd), PM += |alpha| when the decided bit disagrees with HD.
+//
+// The sign of f is taken from the IEEE sign bits (R3), so f(-0, 1) = -0; no decision
+// depends on the sign of a zero.
+// ---------------------------------------------------------------------------------
+struct ArF32 {
+  typedef float T;    // LLR / alpha type
+  typedef float PM;   // path metric type
+  static T from_f32(float x) { return x; }
+  static T f(T a, T b) {
+    T m = std::fabs(a) < std::fabs(b) ? std::fabs(a) : std::fabs(b);
+    return (std::signbit(a) != std::signbit(b)) ? -m : m;
+  }
+  static T g(T a, T b, int u) { return u ? b - a : b + a; }
+  static int hd(T x) { return x < 0 ? 1 : 0; }
+  static PM mag(T x) { return std::fabs(x); }
+  static PM pm_add(PM pm, PM m) { return pm + m; }
+  static double to_double(T x) { return (double)x; }
+};
+
+struct ArF64 {
+  typedef double T;
+  typedef double PM;
+  static T f(T a, T b) {
+    T m = std::fabs(a) < std::fabs(b) ? std::fabs(a) : std::fabs(b);
+    return (std::signbit(a) != std::signbit(b)) ? -m : m;
+  }
+  static T g(T a, T b, int u) { return u ? b - a : b + a; }
+  static int hd(T x) { return x < 0 ? 1 : 0; }
+  static PM mag(T x) { return std::fabs(x); }
+  static PM pm_add(PM pm, PM m) { return pm + m; }
+  static double to_double(T x) { return x; }
+};
+
+// Fixed point (R18): alpha is an integer in [-127, 127]; g saturates to that range;
+// the path metric is a non-negative int16 that saturates at 32767.
+struct ArFix {
+  typedef int T;
+  typedef int PM;
+  static int sat127(int x) { return x > 127 ? 127 : (x < -127 ? -127 : x); }
+  static T f(T a, T b) {
+    int m = std::abs(a) < std::abs(b) ? std::abs(a) : std::abs(b);
+    return ((a < 0) != (b < 0)) ? -m : m;
+  }
+  static T g(T a, T b, int u) { return sat127(u ? b - a : b + a); }
+  static int hd(T x) { return x < 0 ? 1 : 0; }
+  static PM mag(T x) { return std::abs(x); }
+  static PM pm_add(PM pm, PM m) { int s = pm + m; return s > 32767 ? 32767 : s; }
+  static double to_double(T x) { return (double)x; }
+};
+
+template <class A> typename A::T load_llr(const void* p, int j);
+template <> float load_llr<ArF32>(const void* p, int j) { return ((const float*)p)[j]; }
+template <> double load_llr<ArF64>(const void* p, int j) { return ((const double*)p)[j]; }
+template <> int load_llr<ArFix>(const void* p, int j) {
+  return ArFix::sat127((int)((const int8_t*)p)[j]);
+}
+
+// ---------------------------------------------------------------------------------
+// The SC decoding tree with the memory layout of Section 3.1.
+//
+//   alpha memory: stage lambda holds Lambda = 2^lambda LLRs, enough for one branch;
+//                 stage n holds the channel LLRs (eq. llrcalc, first line).
+//   beta memory : stage lambda holds 2*Lambda bits, one half per child of the node
+//                 above: node (lambda, phi) lives at offset (phi mod 2) * Lambda.
+//
+// Node (lambda, phi): stage lambda, branch phi in [0, 2^(n-lambda) - 1] (R4: the
+// paper's "(n - lambda + 1) branches" contradicts its own figures).
+// ---------------------------------------------------------------------------------
+template <class A>
+struct Tree {
+  typedef typename A::T T;
+  int n = 0, N = 0;
+  std::vector<std::vector<T>> alpha;        // alpha[lambda][0..Lambda-1], alpha[n] = root
+  std::vector<std::vector<uint8_t>> beta;   // beta[lambda][0..2*Lambda-1]
+  uint64_t f_ops = 0, g_ops = 0;
+
+  void init(int n_, const void* llr) {
+    n = n_;
+    N = 1 << n;
+    alpha.assign(n + 1, std::vector<T>());
+    beta.assign(n + 1, std::vector<uint8_t>());
+    for (int lam = 0; lam <= n; ++lam) {
+      alpha[lam].assign(1u << lam, T(0));
+      beta[lam].assign(2u << lam, 0);
+    }
+    for (int j = 0; j < N; ++j) alpha[n][j] = load_llr<A>(llr, j);
+  }
+
+  // beta of node (lambda, phi), as stored in the stage-lambda beta memory.
+  uint8_t* beta_of(int lam, int phi) { return beta[lam].data() + (phi & 1) * (1 << lam); }
+
+  // One node of eq. (llrcalc): alpha_v from its parent p = (lambda+1, phi/2) and, for
+  // odd phi, the bits of its left sibling u = (lambda, phi-1).
+  void node_alpha(int lam, int phi) {
+    const int Lam = 1 << lam;
+    const T* ap = alpha[lam + 1].data();
+    T* av = alpha[lam].data();
+    if ((phi & 1) == 0) {
+      for (int i = 0; i < Lam; ++i) av[i] = A::f(ap[i], ap[i + Lam]);
+      f_ops += Lam;
+    } else {
+      const uint8_t* bu = beta_of(lam, phi - 1);
+      for (int i = 0; i < Lam; ++i) av[i] = A::g(ap[i], ap[i + Lam], bu[i]);
+      g_ops += Lam;
+    }
+  }
+
+  // Algorithm 1, recursively_calc_alpha(lambda, phi): walk up while phi is even
+  // (the parent of an even node is stale), then compute the node.
+  void calc_alpha(int lam, int phi) {
+    if (lam == n) return;
+    if ((phi & 1) == 0) calc_alpha(lam + 1, phi >> 1);
+    node_alpha(lam, phi);
+  }
+
+  // Algorithm 4, the SCS-RM variant: after a path switch every ancestor is stale, so
+  // the recursion goes to the root whatever the parity (R5: the listing's loop
+  // variable and its psi are taken as i = 0..Lambda-1 and psi = floor(phi/2)).
+  void calc_alpha_rm(int lam, int phi, bool switched) {
+    if (lam == n) return;
+    if ((phi & 1) == 0 || switched) calc_alpha_rm(lam + 1, phi >> 1, switched);
+    node_alpha(lam, phi);
+  }
+
+  // Algorithm 2, recursively_update_beta(lambda, phi), eq. (bitcalc): once the right
+  // child (odd phi) is known, combine it with its left sibling into the parent and
+  // continue upwards while the parent is itself a right child.
+  void update_beta(int lam, int phi) {
+    if ((phi & 1) == 0) return;
+    if (lam == n) return;
+    const int Lam = 1 << lam;
+    const uint8_t* bl = beta_of(lam, phi - 1);
+    const uint8_t* br = beta_of(lam, phi);
+    uint8_t* bv = beta_of(lam + 1, phi >> 1);
+    for (int i = 0; i < Lam; ++i) {
+      bv[i] = bl[i] ^ br[i];
+      bv[i + Lam] = br[i];
+    }
+    update_beta(lam + 1, phi >> 1);
+  }
+
+  // Leaf bit: beta_(0,i)[0] = u_i (R6: the paper's beta_(0,i)[i] indexes a one-bit
+  // node), then propagate.
+  void set_leaf(int i, uint8_t u) {
+    beta_of(0, i)[0] = u;
+    update_beta(0, i);
+  }
+
+  // Algorithm 3: populate beta with the first PL decided bits of a path.
+  void populate_beta(const uint8_t* u, int PL) {
+    for (int i = 0; i < PL; ++i) set_leaf(i, u[i]);
+  }
+
+  T leaf() const { return alpha[0][0]; }
+};
+
+template <class A>
+int sc_decode_t(int n, const uint8_t* info, const void* llr, uint8_t* u_hat, double* leaf_llr) {
+  Tree<A> t;
+  t.init(n, llr);
+  const int N = 1 << n;
+  // Section 2.2.1: for i = 0..N-1, alpha at leaf i (Algorithm 1), decide by eq. (scest),
+  // propagate the bit (Algorithm 2).
+  for (int i = 0; i < N; ++i) {
+    t.calc_alpha(0, i);
+    typename A::T a = t.leaf();
+    if (leaf_llr) leaf_llr[i] = A::to_double(a);
+    uint8_t u = info[i] ? (uint8_t)A::hd(a) : 0;
+    u_hat[i] = u;
+    t.set_leaf(i, u);
+  }
+  return 0;
+}
+
+template <class A>
+double leaf_llr_t(int n, const void* llr, const uint8_t* prefix, int i) {
+  Tree<A> t;
+  t.init(n, llr);
+  t.populate_beta(prefix, i);
+  t.calc_alpha_rm(0, i, true);
+  return A::to_double(t.leaf());
+}
+
+// ---------------------------------------------------------------------------------
+// CRC-16 (R13): polynomial x^16 + x^12 + x^5 + 1 (0x1021), register starts at 0,
+// bits enter most significant first, no reflection, no final xor.
+// ---------------------------------------------------------------------------------
+uint16_t crc16_bits(const uint8_t* bits, int nbits) {
+  uint16_t reg = 0;
+  for (int k = 0; k < nbits; ++k) {
+    int fb = ((reg >> 15) & 1) ^ (bits[k] & 1);
+    reg = (uint16_t)(reg << 1);
+    if (fb) reg ^= 0x1021;
+  }
+  return reg;
+}
+
+// ---------------------------------------------------------------------------------
+// Successive-cancellation stack decoding, Section 2.2.5 with the reduced-memory
+// scheme of Section 3.3.
+//
+// Readings (R7-R15):
+//  - S is the set of live paths, at most D of them, and includes the path being
+//    extended: each iteration removes the best path from S and inserts its children.
+//  - order: key (PM ascending, PL descending, seq ascending); seq numbers paths in
+//    creation order, the hard-decision child before the flipped child, and a child that
+//    is discarded still uses up its number.
+//  - every leaf estimate is an iteration, frozen positions included.
+//  - when S is full a child replaces the worst path only if its key is strictly
+//    smaller, otherwise the child is dropped.
+//  - the L counter is indexed by the length before the extension, i in [0, N-1]; when
+//    L extensions have been made at length i, every path with PL <= i is removed.
+//  - with a CRC, a length-N path that fails the check is removed and counted; the first
+//    such path is the fallback output; after L failures, or if S empties, decoding
+//    stops with the fallback.
+// ---------------------------------------------------------------------------------
+template <class A>
+struct Path {
+  typename A::PM pm;
+  int pl;
+  uint32_t seq;
+  std::vector<uint8_t> u;
+};
+
+template <class A>
+bool key_less(const Path<A>& a, const Path<A>& b) {
+  if (a.pm < b.pm) return true;
+  if (b.pm < a.pm) return false;
+  if (a.pl != b.pl) return a.pl > b.pl;
+  return a.seq < b.seq;
+}
+
+bool crc_passes(int N, const uint8_t* info, int crc_bits, const uint8_t* u) {
+  if (crc_bits == 0) return true;
+  std::vector<uint8_t> inf;
+  for (int j = 0; j < N; ++j)
+    if (info[j]) inf.push_back(u[j]);
+  const int K = (int)inf.size();
+  const int k = K - crc_bits;
+  uint16_t c = crc16_bits(inf.data(), k);
+  for (int b = 0; b < crc_bits; ++b)
+    if (((c >> (crc_bits - 1 - b)) & 1) != inf[k + b]) return false;
+  return true;
+}
+
+template <class A>
+int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const void* llr,
+                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st) {
+  const int N = 1 << n;
+  Tree<A> t;
+  t.init(n, llr);
+  orc_stats s;
+  std::memset(&s, 0, sizeof s);
+
+  std::vector<Path<A>> S;
+  S.push_back(Path<A>{typename A::PM(0), 0, 0u, std::vector<uint8_t>(N, 0)});
+  uint32_t next_seq = 1;
+  std::vector<int> count(N, 0);  // the L counter per pre-extension length
+  int fails = 0;
+  bool have_fallback = false;
+  Path<A> fallback;
+  // Identity of the path whose alpha/beta state is held in the single tree
+  // (Section 3.3): the hard-decision child of the last extension.
+  bool mem_valid = false;
+  uint32_t mem_seq = 0;
+
+  uint8_t stat = 0;
+  const Path<A>* out = nullptr;
+  Path<A> result;
+
+  for (;;) {
+    if (S.empty()) {  // only reachable after CRC failures, so a fallback exists
+      stat = ORC_ST_FALLBACK | ORC_ST_EXHAUSTED;
+      out = have_fallback ? &fallback : nullptr;
+      break;
+    }
+    // The winner: linear search for the smallest key (Section 3.3).
+    size_t w = 0;
+    for (size_t q = 1; q < S.size(); ++q)
+      if (key_less<A>(S[q], S[w])) w = q;
+    Path<A> p = S[w];
+    S.erase(S.begin() + (long)w);
+
+    if (p.pl == N) {  // termination / CRC, Section 2.2.5
+      ++s.completions;
+      if (crc_passes(N, info, crc_bits, p.u.data())) {
+        result = p;
+        out = &result;
+        stat = ORC_ST_OK;
+        break;
+      }
+      if (!have_fallback) {
+        fallback = p;
+        have_fallback = true;
+      }
+      if (++fails >= L) {
+        stat = ORC_ST_FALLBACK;
+        out = &fallback;
+        break;
+      }
+      continue;
+    }
+
+    const int i = p.pl;
+    ++s.iterations;
+    s.sc_elems += (i == 0) ? (uint64_t)(N - 1) : ((2ull << __builtin_ctz((unsigned)i)) - 1);
+
+    // alpha at leaf i for path p.
+    if (mem_valid && p.seq == mem_seq) {
+      t.calc_alpha(0, i);                 // Algorithm 1: the SC schedule continues
+    } else {
+      ++s.switches;
+      t.populate_beta(p.u.data(), i);     // Algorithm 3
+      t.calc_alpha_rm(0, i, true);        // Algorithm 4
+    }
+    const typename A::T a = t.leaf();
+    const int h = A::hd(a);
+    const typename A::PM m = A::mag(a);
+
+    // Children (eq. PMupd): an information bit splits, a frozen bit (value 0) does not.
+    Path<A> c0 = p;
+    c0.pl = i + 1;
+    c0.seq = next_seq++;
+    std::vector<Path<A>> kids;
+    if (info[i]) {
+      c0.u[i] = (uint8_t)h;
+      Path<A> c1 = p;
+      c1.pl = i + 1;
+      c1.u[i] = (uint8_t)(1 - h);
+      c1.pm = A::pm_add(p.pm, m);
+      c1.seq = next_seq++;
+      kids.push_back(c0);
+      kids.push_back(c1);
+    } else {
+      c0.u[i] = 0;
+      if (h) c0.pm = A::pm_add(p.pm, m);
+      kids.push_back(c0);
+    }
+    // The tree now follows the first child: propagate its bit (Algorithm 2).
+    t.set_leaf(i, kids[0].u[i]);
+    mem_valid = true;
+    mem_seq = kids[0].seq;
+
+    // Insert, replacing the worst path of a full stack only by a better one.
+    for (auto& c : kids) {
+      if ((int)S.size() < D) {
+        S.push_back(c);
+        continue;
+      }
+      size_t wq = 0;
+      for (size_t q = 1; q < S.size(); ++q)
+        if (key_less<A>(S[wq], S[q])) wq = q;
+      if (key_less<A>(c, S[wq])) {
+        S[wq] = c;
+        ++s.evictions;
+      } else {
+        ++s.drops;
+      }
+    }
+
+    // L-counter pruning.
+    if (++count[i] == L) {
+      ++s.prunes;
+      std::vector<Path<A>> keep;
+      for (auto& q : S)
+        if (q.pl > i) keep.push_back(q);
+      S.swap(keep);
+    }
+  }
+
+  s.f_ops = t.f_ops;
+  s.g_ops = t.g_ops;
+  if (out) {
+    std::memcpy(u_hat, out->u.data(), (size_t)N);
+    if (pm_out) *pm_out = (double)out->pm;
+  } else {
+    std::memset(u_hat, 0, (size_t)N);
+    if (pm_out) *pm_out = 0.0;
+  }
+  *status = stat;
+  if (st) *st = s;
+  return 0;
+}
+
+// Bhattacharyya parameters in the log domain (R17): z0 = exp(-R * Eb/N0) for BPSK on
+// AWGN; the "minus" (f) child of z is 2z - z^2 and the "plus" (g) child is z^2.
+// Indices: the children of index j are 2j (minus) and 2j+1 (plus), so the first split
+// is the most significant bit of the leaf index, as in the tree of eq. (llrcalc).
+void bhatta_log(int n, double rate, double design_db, double* lz) {
+  const int N = 1 << n;
+  std::vector<double> cur(1, -rate * std::pow(10.0, design_db / 10.0));
+  for (int level = 0; level < n; ++level) {
+    std::vector<double> nxt(cur.size() * 2);
+    for (size_t j = 0; j < cur.size(); ++j) {
+      const double l = cur[j];
+      // ln(2z - z^2) = ln z + ln(2 - z), and 2 - z = 1 - (z - 1) = 1 - expm1(ln z).
+      nxt[2 * j] = l + std::log1p(-std::expm1(l));
+      nxt[2 * j + 1] = 2.0 * l;                    // ln(z^2)
+    }
+    cur.swap(nxt);
+  }
+  for (int j = 0; j < N; ++j) lz[j] = cur[j];
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_bhattacharyya_log(int N, double rate, double design_ebn0_db, double* lz) {
+  const int n = log2_exact(N);
+  if (n < 0 || !lz) return -1;
+  bhatta_log(n, rate, design_ebn0_db, lz);
+  return 0;
+}
+
+int orc_construct(int N, int K, double design_ebn0_db, uint8_t* info_mask) {
+  const int n = log2_exact(N);
+  if (n < 0 || K < 0 || K > N || !info_mask) return -1;
+  std::vector<double> lz(N);
+  bhatta_log(n, (double)K / N, design_ebn0_db, lz.data());
+  std::vector<int> idx(N);
+  for (int j = 0; j < N; ++j) idx[j] = j;
+  // Most reliable first: smaller parameter, then larger index.
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (lz[a] != lz[b]) return lz[a] < lz[b];
+    return a > b;
+  });
+  std::memset(info_mask, 0, (size_t)N);
+  for (int k = 0; k < K; ++k) info_mask[idx[k]] = 1;
+  return 0;
+}
+
+uint16_t orc_crc16_bits(const uint8_t* bits, int nbits) { return crc16_bits(bits, nbits); }
+
+int orc_polar_transform(int N, const uint8_t* u, uint8_t* c) {
+  // Section 2.1: c = u F^{(x)n}, drawn as the n-stage XOR tree of the encoder figure:
+  // at stage s (distance 2^s) every upper wire j takes the XOR of wire j + 2^s.
+  if (log2_exact(N) < 0) return -1;
+  std::vector<uint8_t> x(u, u + N);
+  for (int s = 1; s < N; s <<= 1)
+    for (int j = 0; j < N; ++j)
+      if ((j & s) == 0) x[j] ^= x[j + s];
+  std::memcpy(c, x.data(), (size_t)N);
+  return 0;
+}
+
+int orc_encode_batch(int N, const uint8_t* info_mask, int crc_bits, const uint8_t* payload,
+                     int64_t B, uint8_t* codeword) {
+  if (log2_exact(N) < 0 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  std::vector<int> pos;
+  for (int j = 0; j < N; ++j)
+    if (info_mask[j]) pos.push_back(j);
+  const int K = (int)pos.size();
+  const int k = K - crc_bits;
+  if (k < 0) return -1;
+  std::vector<uint8_t> u(N), msg(K);
+  for (int64_t b = 0; b < B; ++b) {
+    const uint8_t* pl = payload + b * k;
+    for (int j = 0; j < k; ++j) msg[j] = pl[j] & 1;
+    if (crc_bits) {
+      uint16_t c = crc16_bits(msg.data(), k);
+      for (int j = 0; j < crc_bits; ++j) msg[k + j] = (uint8_t)((c >> (crc_bits - 1 - j)) & 1);
+    }
+    // Section 2.1: message bits at the indices of A, zeros elsewhere.
+    std::fill(u.begin(), u.end(), 0);
+    for (int j = 0; j < K; ++j) u[pos[j]] = msg[j];
+    orc_polar_transform(N, u.data(), codeword + b * N);
+  }
+  return 0;
+}
+
+int orc_sc_decode(int mode, int N, const uint8_t* info_mask, const void* llr, uint8_t* u_hat,
+                  double* leaf_llr) {
+  const int n = log2_exact(N);
+  if (n < 0) return -1;
+  switch (mode) {
+    case ORC_F32: return sc_decode_t<ArF32>(n, info_mask, llr, u_hat, leaf_llr);
+    case ORC_F64: return sc_decode_t<ArF64>(n, info_mask, llr, u_hat, leaf_llr);
+    case ORC_FIX: return sc_decode_t<ArFix>(n, info_mask, llr, u_hat, leaf_llr);
+  }
+  return -1;
+}
+
+double orc_leaf_llr(int mode, int N, const void* llr, const uint8_t* prefix, int i) {
+  const int n = log2_exact(N);
+  if (n < 0 || i < 0 || i >= N) return NAN;
+  switch (mode) {
+    case ORC_F32: return leaf_llr_t<ArF32>(n, llr, prefix, i);
+    case ORC_F64: return leaf_llr_t<ArF64>(n, llr, prefix, i);
+    case ORC_FIX: return leaf_llr_t<ArFix>(n, llr, prefix, i);
+  }
+  return NAN;
+}
+
+int orc_scs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                   orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  switch (mode) {
+    case ORC_F32: return scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
+    case ORC_F64: return scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
+    case ORC_FIX: return scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
+  }
+  return -1;
+}
+
+int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                         const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
+                         orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0) return -1;
+  const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
+  int K = 0;
+  for (int j = 0; j < N; ++j) K += info_mask[j] ? 1 : 0;
+  const int k = K - crc_bits;
+  std::vector<uint8_t> u(N);
+  for (int64_t b = 0; b < B; ++b) {
+    int rc = orc_scs_decode(mode, N, info_mask, crc_bits, D, L,
+                            (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
+                            nullptr, st ? st + b : nullptr);
+    if (rc) return rc;
+    int q = 0;
+    for (int j = 0; j < N && q < k; ++j)
+      if (info_mask[j]) payload[b * k + q++] = u[j];
+  }
+  return 0;
+}
+
+int orc_ml_decode(int N, const uint8_t* info_mask, const double* llr, double* disc_min,
+                  int64_t* n_min, uint8_t* minimisers, int64_t max_out) {
+  if (log2_exact(N) < 0) return -1;
+  std::vector<int> pos;
+  for (int j = 0; j < N; ++j)
+    if (info_mask[j]) pos.push_back(j);
+  const int K = (int)pos.size();
+  if (K > 20) return -1;
+  std::vector<uint8_t> u(N), c(N);
+  double best = INFINITY;
+  int64_t cnt = 0;
+  for (uint64_t m = 0; m < (1ull << K); ++m) {
+    std::fill(u.begin(), u.end(), 0);
+    for (int j = 0; j < K; ++j) u[pos[j]] = (uint8_t)((m >> j) & 1);
+    orc_polar_transform(N, u.data(), c.data());
+    double d = 0.0;
+    for (int j = 0; j < N; ++j)
+      if (c[j] != (llr[j] < 0 ? 1 : 0)) d += std::fabs(llr[j]);
+    if (d < best) {
+      best = d;
+      cnt = 0;
+    }
+    if (d == best) {
+      if (cnt < max_out && minimisers) std::memcpy(minimisers + cnt * N, u.data(), (size_t)N);
+      ++cnt;
+    }
+  }
+  *disc_min = best;
+  *n_min = cnt;
+  return 0;
+}
+
+}  // extern "C"
