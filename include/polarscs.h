@@ -1,0 +1,163 @@
+/*
+ * polarscs.h -- C-ABI of the MI355X (gfx950) successive-cancellation stack decoder.
+ *
+ * Polar codes PC(N, K) and their SCS decoding as in H. Aurora, W. Gross, "Towards
+ * Practical Software Stack Decoding of Polar Codes" (Section 2.1 for the code, Section
+ * 2.2 for SC / SCS decoding, Section 3 for the tree memory and the reduced-memory stack
+ * scheme).  Plain pointers and sizes only; no framework types cross this boundary.
+ *
+ * Conventions shared by every call
+ *   - Bits are uint8_t values 0 or 1, one per byte.
+ *   - N = 2^n with 2 <= N <= 2048.  K counts every information position, CRC bits
+ *     included; the first K - crc_bits information positions (ascending index) carry
+ *     the payload and the last crc_bits carry the CRC remainder, most significant bit
+ *     first.
+ *   - CRC: crc_bits is 0 or 16; CRC-16 with polynomial 0x1021, initial register 0, bits
+ *     most significant first, no reflection, no final xor (check value 0x31C3 over the
+ *     ASCII string "123456789").
+ *   - Return value: POLAR_OK (0) or a negative POLAR_E* code.  Argument errors are
+ *     detected on the host before anything is enqueued, and nothing is written then.
+ *   - Device pointers must be valid for the device of the context (or the current
+ *     device for calls without a context) and stay alive until the stream reaches the
+ *     enqueued work.  The caller owns every buffer it passes.
+ */
+#ifndef POLARSCS_H
+#define POLARSCS_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  POLAR_OK = 0,
+  POLAR_EINVAL = -1,       /* invalid argument */
+  POLAR_ENOMEM = -2,       /* host or device allocation failed */
+  POLAR_EDEVICE = -3,      /* a HIP runtime call failed */
+  POLAR_EUNSUPPORTED = -4  /* valid request outside what this build supports */
+};
+
+/* Per-frame status bits written by the decoders. */
+enum {
+  SCS_STATUS_OK = 1,        /* output path passed the CRC (or there is no CRC) */
+  SCS_STATUS_FALLBACK = 2,  /* every complete path failed the CRC; the first one is output */
+  SCS_STATUS_EXHAUSTED = 4  /* decoding stopped because the stack emptied */
+};
+
+/* LLR element types. */
+enum { SCS_LLR_F32 = 0, SCS_LLR_I8 = 1 };
+
+/* -- code construction (Section 2.1) ------------------------------------------------ */
+
+typedef struct polar_code polar_code; /* opaque, host-owned, immutable once built */
+
+/* Build PC(N, K): the information set is the K synthetic channels with the smallest
+ * Bhattacharyya parameter for BPSK on AWGN at design_ebn0_db with rate K / N
+ * (z0 = exp(-R Eb/N0); the f child of z is 2z - z^2, the g child is z^2; the first
+ * split is the most significant bit of the index; ties go to the larger index).  The
+ * paper takes its set from the 3GPP sequence; this construction stands in for it.
+ * crc_bits: 0 or 16, counted inside K (K > crc_bits).  On success *out receives a new
+ * code released with polar_code_free.  Errors: POLAR_EINVAL for N not a power of two in
+ * [2, 2048], K outside [1, N], crc_bits not 0/16 or >= K, or a NULL out. */
+int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_db,
+                    polar_code** out);
+
+/* Read back the parameters; any output pointer may be NULL.  info_mask_or_null, if
+ * given, receives N bytes: 1 for an information position, 0 for a frozen one. */
+int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,
+                     uint8_t* info_mask_or_null);
+
+void polar_code_free(polar_code* code);
+
+/* -- encoding (Section 2.1: u at the information set, zeros elsewhere, c = u F^(x)n) -- */
+
+/* Host encoder.  payload: B x (K - crc_bits) bits, row-major; codeword: B x N bits,
+ * row-major.  The CRC remainder of each payload is appended when crc_bits = 16. */
+int polar_encode(const polar_code* code, const uint8_t* payload, uint8_t* codeword,
+                 int64_t B);
+
+/* Device encoder with the same layout and result, enqueued on hip_stream (a
+ * hipStream_t; NULL = the default stream) of the current device.  Allocates nothing; the
+ * code's tables travel as kernel arguments. */
+int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
+                        uint8_t* codeword_dev, int64_t B, void* hip_stream);
+
+/* -- SCS decoding (Section 2.2.5; reduced-memory stack of Section 3.3) -------------- */
+
+typedef struct scs_ctx scs_ctx; /* per-device decoder context */
+
+/* Create a context on HIP device `device`.  It owns the device-side code tables used by
+ * mixed batches and a small work counter; it allocates nothing once created except when
+ * a mixed batch needs more table space than any earlier one. */
+int scs_ctx_create(int device, scs_ctx** out);
+void scs_ctx_destroy(scs_ctx* ctx);
+
+/* Per-frame counters (optional output of the decoders), one record per frame. */
+typedef struct {
+  uint32_t iterations;  /* leaf estimates (path extensions) */
+  uint32_t switches;    /* extensions whose path was not the one held in the tree */
+  uint32_t completions; /* length-N paths taken off the stack */
+  uint32_t sc_elems;    /* sum of 2^(tz(i)+1) - 1 over extensions at i > 0, N - 1 at i = 0 */
+  uint32_t fg_elems;    /* f/g element evaluations actually performed by the kernel */
+  uint32_t evictions;   /* worst paths replaced in a full stack */
+  uint32_t drops;       /* children discarded by a full stack */
+  uint32_t prunes;      /* L-counter prune events */
+} scs_stats;
+
+/* Decode n_frames frames of one code with stack depth D and list parameter L.
+ *
+ * Per frame the decoder runs the stack search of Section 2.2.5: the best path (key:
+ * path metric ascending, length descending, creation order ascending) is extended by
+ * one leaf estimate (eq. llrcalc / scest), an information bit yields the hard-decision
+ * child and the flipped child (eq. PMupd), a full stack keeps the D best paths, and
+ * after L extensions at one length every path that short or shorter is dropped.  A
+ * complete path is output if it passes the CRC; after L failures (or an empty stack)
+ * the first complete path is output with SCS_STATUS_FALLBACK.
+ *
+ *   llr_dtype   SCS_LLR_F32: float LLRs, binary32 tree arithmetic;
+ *               SCS_LLR_I8 : int8 LLRs in [-127, 127], saturating int8 tree, int16
+ *                            saturating path metric.
+ *   llr_dev     n_frames x N elements, row-major (frame f at f * N).
+ *   payload_dev n_frames x (K - crc_bits) output bits, row-major.
+ *   status_dev  n_frames status bytes (SCS_STATUS_*).
+ *   stats_dev   NULL, or n_frames scs_stats records.
+ *   D in [1, 64], L in [1, 255].
+ * Enqueued on hip_stream of the context's device; returns before the work runs.  The
+ * result of a frame depends only on that frame's LLRs and (code, D, L).  Non-finite
+ * LLRs give an unspecified output but the kernel still terminates: every frame stops
+ * after at most L * N + L iterations. */
+int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
+                     int32_t llr_dtype, const void* llr_dev, int64_t n_frames,
+                     uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
+                     void* hip_stream);
+
+/* One frame of a mixed batch. */
+typedef struct {
+  int32_t code;    /* index into the codes array */
+  int32_t D;       /* stack depth, [1, 64] */
+  int32_t L;       /* list parameter, [1, 255] */
+  int32_t _pad;    /* must be 0 */
+  int64_t llr_off; /* element offset of the frame's N LLRs in llr_dev */
+  int64_t out_off; /* byte offset of the frame's K - crc_bits payload bits */
+} scs_frame;
+
+/* Decode frames of different codes, depths and list sizes in one persistent launch.
+ * frames_host: n_frames descriptors in host memory (validated on the host, then copied
+ * into the context's device buffer on hip_stream).  Frame f writes status_dev[f] and,
+ * if stats_dev is not NULL, stats_dev[f].  The result of every frame equals what
+ * scs_decode_batch gives for it alone.  Errors: POLAR_EINVAL for a bad code index, D, L,
+ * _pad, or an offset that is negative. */
+int scs_decode_mixed(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                     const scs_frame* frames_host, int64_t n_frames, int32_t llr_dtype,
+                     const void* llr_dev, uint8_t* payload_dev, uint8_t* status_dev,
+                     scs_stats* stats_dev, void* hip_stream);
+
+/* Last HIP error seen by a call on this context (POLAR_OK if none), then cleared. */
+int scs_ctx_last_error(scs_ctx* ctx);
+
+/* Text for a status code. */
+const char* polar_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

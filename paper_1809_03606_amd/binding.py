@@ -1,0 +1,248 @@
+"""Thin ctypes binding of ``libpolarscs.so`` (argument marshalling only).
+
+Every decoding step runs in the library's HIP kernels; this module only converts
+arguments (numpy arrays for host buffers, torch tensors or raw addresses for device
+buffers, torch streams for ``hip_stream``).  If the library has not been built the first
+call raises: there is no fallback path.
+
+The functions keep the C names (``polar_construct``, ``polar_encode``,
+``scs_decode_batch``, ...); ``PolarCode`` and ``ScsContext`` wrap the opaque handles.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolarscs.so")
+
+POLAR_OK, POLAR_EINVAL, POLAR_ENOMEM, POLAR_EDEVICE, POLAR_EUNSUPPORTED = 0, -1, -2, -3, -4
+SCS_STATUS_OK, SCS_STATUS_FALLBACK, SCS_STATUS_EXHAUSTED = 1, 2, 4
+SCS_LLR_F32, SCS_LLR_I8 = 0, 1
+
+EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
+           "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
+           "scs_decode_mixed", "scs_ctx_last_error", "polar_strerror")
+
+STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
+                "drops", "prunes")
+STATS_DTYPE = np.dtype([(f, np.uint32) for f in STATS_FIELDS])
+
+FRAME_DTYPE = np.dtype([("code", np.int32), ("D", np.int32), ("L", np.int32), ("_pad", np.int32),
+                        ("llr_off", np.int64), ("out_off", np.int64)])
+
+
+class ScsFrame(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("D", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("_pad", ctypes.c_int32), ("llr_off", ctypes.c_int64), ("out_off", ctypes.c_int64)]
+
+
+class PolarError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load the HIP library; raises if it is missing (build it first)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError("libpolarscs.so is not built: run `python -m "
+                                   "paper_1809_03606_amd.build` (no CPU fallback exists)")
+            L = ctypes.CDLL(_LIB_PATH)
+            vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+            L.polar_construct.argtypes = [i32, i32, i32, dbl, ctypes.POINTER(vp)]
+            L.polar_code_query.argtypes = [vp, vp, vp, vp, vp]
+            L.polar_code_free.argtypes = [vp]
+            L.polar_code_free.restype = None
+            L.polar_encode.argtypes = [vp, vp, vp, i64]
+            L.polar_encode_device.argtypes = [vp, vp, vp, i64, vp]
+            L.scs_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+            L.scs_ctx_destroy.argtypes = [vp]
+            L.scs_ctx_destroy.restype = None
+            L.scs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
+            L.scs_decode_mixed.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
+            L.scs_ctx_last_error.argtypes = [vp]
+            L.polar_strerror.argtypes = [ctypes.c_int]
+            L.polar_strerror.restype = ctypes.c_char_p
+            for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
+                      "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
+                      "scs_ctx_last_error"):
+                getattr(L, n).restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().polar_strerror(int(code)).decode()
+    except Exception:  # the library itself may be what is missing
+        return "status %d" % code
+
+
+def _check(rc: int, what: str):
+    if rc != POLAR_OK:
+        raise PolarError(rc, what)
+
+
+def _addr(x) -> int | None:
+    """Device or host address of a torch tensor / numpy array / int (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return int(x.data_ptr())
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)  # torch.cuda.Stream
+
+
+# -- raw C-ABI names ----------------------------------------------------------------
+
+def polar_construct(N: int, K: int, crc_bits: int, design_ebn0_db: float) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().polar_construct(N, K, crc_bits, float(design_ebn0_db), ctypes.byref(h)),
+           "polar_construct")
+    return h.value
+
+
+def polar_code_query(handle: int):
+    N, K, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().polar_code_query(handle, ctypes.byref(N), ctypes.byref(K), ctypes.byref(r), None),
+           "polar_code_query")
+    mask = np.zeros(N.value, np.uint8)
+    _check(lib().polar_code_query(handle, None, None, None, mask.ctypes.data), "polar_code_query")
+    return N.value, K.value, r.value, mask
+
+
+def polar_code_free(handle: int):
+    lib().polar_code_free(handle)
+
+
+def polar_encode(handle: int, payload: np.ndarray, codeword: np.ndarray):
+    assert payload.flags.c_contiguous and codeword.flags.c_contiguous
+    assert payload.dtype == np.uint8 and codeword.dtype == np.uint8
+    _check(lib().polar_encode(handle, _addr(payload), _addr(codeword), int(codeword.shape[0])),
+           "polar_encode")
+
+
+def polar_encode_device(handle: int, payload_dev, codeword_dev, B: int, stream=None):
+    _check(lib().polar_encode_device(handle, _addr(payload_dev), _addr(codeword_dev), int(B),
+                                     _stream(stream)), "polar_encode_device")
+
+
+def scs_ctx_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().scs_ctx_create(int(device), ctypes.byref(h)), "scs_ctx_create")
+    return h.value
+
+
+def scs_ctx_destroy(ctx: int):
+    lib().scs_ctx_destroy(ctx)
+
+
+def scs_decode_batch(ctx: int, code: int, D: int, L: int, llr_dtype: int, llr_dev, n_frames: int,
+                     payload_dev, status_dev, stats_dev=None, stream=None):
+    _check(lib().scs_decode_batch(ctx, code, int(D), int(L), int(llr_dtype), _addr(llr_dev),
+                                  int(n_frames), _addr(payload_dev), _addr(status_dev),
+                                  _addr(stats_dev), _stream(stream)), "scs_decode_batch")
+
+
+def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_dev, payload_dev,
+                     status_dev, stats_dev=None, stream=None):
+    arr = (ctypes.c_void_p * len(codes))(*codes)
+    fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    _check(lib().scs_decode_mixed(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
+                                  fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
+                                  _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
+                                  _addr(stats_dev), _stream(stream)), "scs_decode_mixed")
+
+
+def scs_ctx_last_error(ctx: int) -> int:
+    return int(lib().scs_ctx_last_error(ctx))
+
+
+# -- handle wrappers -----------------------------------------------------------------
+
+class PolarCode:
+    """A constructed PC(N, K) (Bhattacharyya set at design_db), CRC bits inside K."""
+
+    def __init__(self, N: int, K: int, crc_bits: int = 0, design_db: float = 2.0):
+        self.handle = polar_construct(N, K, crc_bits, design_db)
+        self.N, self.K, self.crc_bits, self.info_mask = polar_code_query(self.handle)
+        self.design_db = design_db
+
+    @property
+    def payload_bits(self) -> int:
+        return self.K - self.crc_bits
+
+    @property
+    def rate(self) -> float:
+        return self.K / self.N
+
+    def encode(self, payload: np.ndarray) -> np.ndarray:
+        payload = np.ascontiguousarray(payload, dtype=np.uint8).reshape(-1, self.payload_bits)
+        cw = np.zeros((payload.shape[0], self.N), np.uint8)
+        polar_encode(self.handle, payload, cw)
+        return cw
+
+    def encode_device(self, payload_dev, codeword_dev, stream=None):
+        polar_encode_device(self.handle, payload_dev, codeword_dev, payload_dev.shape[0], stream)
+
+    def close(self):
+        if self.handle:
+            polar_code_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ScsContext:
+    def __init__(self, device: int = 0):
+        self.handle = scs_ctx_create(device)
+        self.device = device
+
+    def decode(self, code: PolarCode, D: int, L: int, llr_dev, payload_dev, status_dev,
+               stats_dev=None, stream=None):
+        import torch  # device buffers are torch tensors here
+
+        dtype = SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8
+        if llr_dev.dtype not in (torch.float32, torch.int8):
+            raise TypeError("LLRs must be float32 or int8")
+        n = llr_dev.numel() // code.N
+        scs_decode_batch(self.handle, code.handle, D, L, dtype, llr_dev, n, payload_dev,
+                         status_dev, stats_dev, stream)
+
+    def close(self):
+        if self.handle:
+            scs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

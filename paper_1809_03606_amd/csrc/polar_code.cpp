@@ -1,0 +1,199 @@
+// Host half of the C-ABI: code construction, CRC-16, host encoder.
+//
+// Section 2.1 of Aurora & Gross defines PC(N, K): message bits at the information set,
+// zeros at the frozen set, codeword c = u F^(x)n.  The information set here comes from a
+// Bhattacharyya construction (the paper uses the 3GPP sequence, which this library does
+// not ship).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "polar_code.h"
+#include "polarscs.h"
+
+namespace polarscs {
+
+namespace {
+
+std::atomic<uint64_t> g_next_uid{1};
+
+// Table for CRC-16 with polynomial 0x1021 processed a byte at a time, most significant
+// bit first: entry v is the register after shifting the byte v through an all-zero
+// register.
+struct Crc16Table {
+  uint16_t t[256];
+  Crc16Table() {
+    for (int v = 0; v < 256; ++v) {
+      uint32_t r = (uint32_t)v << 8;
+      for (int b = 0; b < 8; ++b) r = (r & 0x8000) ? ((r << 1) ^ 0x1021) : (r << 1);
+      t[v] = (uint16_t)r;
+    }
+  }
+};
+const Crc16Table& crc_table() {
+  static const Crc16Table tab;
+  return tab;
+}
+
+// log of the Bhattacharyya parameter of synthetic channel j: start from the channel
+// value and, from the most significant index bit down, apply the f transform
+// (z -> 2z - z^2) for a 0 bit and the g transform (z -> z^2) for a 1 bit.
+double log_bhattacharyya(int j, int logn, double lz0) {
+  double lz = lz0;
+  for (int b = logn - 1; b >= 0; --b) {
+    if ((j >> b) & 1) {
+      lz = 2.0 * lz;
+    } else {
+      // ln(2z - z^2) = ln z + ln(1 + (1 - z)), with 1 - z = -expm1(ln z)
+      lz = lz + std::log1p(-std::expm1(lz));
+    }
+  }
+  return lz;
+}
+
+}  // namespace
+
+uint16_t crc16_payload(const uint8_t* bits, int nbits) {
+  const Crc16Table& T = crc_table();
+  uint16_t reg = 0;
+  int k = 0;
+  for (; k + 8 <= nbits; k += 8) {
+    uint32_t byte = 0;
+    for (int b = 0; b < 8; ++b) byte = (byte << 1) | (bits[k + b] & 1u);
+    reg = (uint16_t)((reg << 8) ^ T.t[((reg >> 8) ^ byte) & 0xFF]);
+  }
+  for (; k < nbits; ++k) {
+    const uint32_t top = ((reg >> 15) ^ bits[k]) & 1u;
+    reg = (uint16_t)(reg << 1);
+    if (top) reg ^= 0x1021;
+  }
+  return reg;
+}
+
+}  // namespace polarscs
+
+using polarscs::crc16_payload;
+
+extern "C" {
+
+const char* polar_strerror(int code) {
+  switch (code) {
+    case POLAR_OK: return "ok";
+    case POLAR_EINVAL: return "invalid argument";
+    case POLAR_ENOMEM: return "out of memory";
+    case POLAR_EDEVICE: return "HIP runtime error";
+    case POLAR_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_db,
+                    polar_code** out) {
+  if (!out) return POLAR_EINVAL;
+  *out = nullptr;
+  if (N < 2 || N > 2048 || (N & (N - 1)) != 0) return POLAR_EINVAL;
+  if (K < 1 || K > N) return POLAR_EINVAL;
+  if (crc_bits != 0 && crc_bits != 16) return POLAR_EINVAL;
+  if (crc_bits >= K) return POLAR_EINVAL;
+  if (!std::isfinite(design_ebn0_db)) return POLAR_EINVAL;
+
+  polar_code* c = new (std::nothrow) polar_code;
+  if (!c) return POLAR_ENOMEM;
+  c->N = N;
+  c->K = K;
+  c->crc = crc_bits;
+  c->logn = 0;
+  while ((1 << c->logn) < N) ++c->logn;
+  c->uid = polarscs::g_next_uid.fetch_add(1);
+
+  const double lz0 = -((double)K / N) * std::pow(10.0, design_ebn0_db / 10.0);
+  std::vector<double> lz(N);
+  for (int j = 0; j < N; ++j) lz[j] = polarscs::log_bhattacharyya(j, c->logn, lz0);
+  std::vector<int32_t> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  // K most reliable: smallest parameter first; equal parameters prefer the larger index.
+  std::partial_sort(order.begin(), order.begin() + K, order.end(), [&](int32_t a, int32_t b) {
+    return lz[a] < lz[b] || (lz[a] == lz[b] && a > b);
+  });
+  c->info.assign(N, 0);
+  for (int k = 0; k < K; ++k) c->info[order[k]] = 1;
+  for (int j = 0; j < N; ++j)
+    if (c->info[j]) c->info_pos.push_back(j);
+  int run = 0;
+  for (int w = 0; w < 64; ++w) {
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int j = 32 * w + b;
+      if (j < N && c->info[j]) word |= 1u << b;
+    }
+    c->info_words[w] = word;
+    c->info_prefix[w] = (uint16_t)run;
+    run += __builtin_popcount(word);
+  }
+  // The CRC has no initial value and no final xor, so it is linear over GF(2): the
+  // remainder of a payload is the xor of the remainders of its one-bits.
+  const int kp = c->payload_bits();
+  c->crc_unit.assign(kp, 0);
+  if (crc_bits) {
+    std::vector<uint8_t> e(kp, 0);
+    for (int p = 0; p < kp; ++p) {
+      e[p] = 1;
+      c->crc_unit[p] = crc16_payload(e.data(), kp);
+      e[p] = 0;
+    }
+  }
+  *out = c;
+  return POLAR_OK;
+}
+
+int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,
+                     uint8_t* info_mask_or_null) {
+  if (!code) return POLAR_EINVAL;
+  if (N) *N = code->N;
+  if (K) *K = code->K;
+  if (crc_bits) *crc_bits = code->crc;
+  if (info_mask_or_null) std::memcpy(info_mask_or_null, code->info.data(), (size_t)code->N);
+  return POLAR_OK;
+}
+
+void polar_code_free(polar_code* code) { delete code; }
+
+int polar_encode(const polar_code* code, const uint8_t* payload, uint8_t* codeword,
+                 int64_t B) {
+  if (!code || B < 0) return POLAR_EINVAL;
+  if (B == 0) return POLAR_OK;
+  if (!payload || !codeword) return POLAR_EINVAL;
+  const int N = code->N, kp = code->payload_bits();
+  const int nw = (N + 63) / 64;
+  std::vector<uint64_t> x(nw);
+  std::vector<uint8_t> msg(code->K);
+  for (int64_t f = 0; f < B; ++f) {
+    const uint8_t* pl = payload + f * kp;
+    for (int j = 0; j < kp; ++j) msg[j] = pl[j] & 1;
+    if (code->crc) {
+      const uint16_t r = crc16_payload(msg.data(), kp);
+      for (int j = 0; j < code->crc; ++j) msg[kp + j] = (uint8_t)((r >> (code->crc - 1 - j)) & 1);
+    }
+    std::fill(x.begin(), x.end(), 0);
+    for (int j = 0; j < code->K; ++j)
+      if (msg[j]) x[code->info_pos[j] >> 6] |= 1ull << (code->info_pos[j] & 63);
+    // u F^(x)n as butterflies on packed bits: position j takes j xor (j + d) for every
+    // distance d with bit d of j clear.  Within a 64-bit word that is a masked shift.
+    static const uint64_t kLow[6] = {0x5555555555555555ull, 0x3333333333333333ull,
+                                     0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
+                                     0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+    for (int s = 0; s < 6 && (1 << s) < N; ++s)
+      for (int w = 0; w < nw; ++w) x[w] ^= (x[w] >> (1 << s)) & kLow[s];
+    for (int dw = 1; dw < nw; dw <<= 1)
+      for (int w = 0; w < nw; ++w)
+        if ((w & dw) == 0) x[w] ^= x[w + dw];
+    uint8_t* cw = codeword + f * N;
+    for (int j = 0; j < N; ++j) cw[j] = (uint8_t)((x[j >> 6] >> (j & 63)) & 1);
+  }
+  return POLAR_OK;
+}
+
+}  // extern "C"

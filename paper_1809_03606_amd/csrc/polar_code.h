@@ -1,0 +1,25 @@
+// Internal definition of the opaque polar_code object, shared by the host encoder and the
+// HIP launchers of this library.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+struct polar_code {
+  int32_t N = 0;      // code length, 2^logn
+  int32_t K = 0;      // information positions, CRC bits included
+  int32_t crc = 0;    // 0 or 16
+  int32_t logn = 0;
+  uint64_t uid = 0;   // process-unique id (device table caches key on it)
+  std::vector<uint8_t> info;     // N bytes, 1 = information position
+  std::vector<int32_t> info_pos; // K positions, ascending
+  uint32_t info_words[64] = {};  // info mask, bit j of word w = position 32 w + j
+  uint16_t info_prefix[64] = {}; // number of information positions before word w
+  std::vector<uint16_t> crc_unit; // CRC remainder of the unit payload vector e_p, p < K - crc
+  int32_t payload_bits() const { return K - crc; }
+  int32_t words() const { return N >= 32 ? N / 32 : 1; }
+};
+
+namespace polarscs {
+uint16_t crc16_payload(const uint8_t* bits, int nbits);
+}

@@ -1,0 +1,771 @@
+// Batched successive-cancellation stack (SCS) decoding of polar codes on gfx950.
+//
+// Method: Aurora & Gross, "Towards Practical Software Stack Decoding of Polar Codes",
+// Section 2.2.5 (stack search, L-counter pruning, CRC termination), Section 2.2.1
+// (min-sum f/g, eq. minsum; leaf decision, eq. scest; partial sums, eq. bitcalc) and the
+// reduced-memory stack of Section 3.3 (one alpha/beta state, paths store only PM, PL and
+// their decided bits; a path switch recomputes the tree).
+//
+// Mapping (one wavefront of 64 lanes decodes one frame):
+//   * alpha tree in VGPRs: stage lambda (Lambda = 2^lambda values) puts value e in lane
+//     e mod 64 of register e / 64, so for Lambda >= 64 the f/g operands of a value sit in
+//     the same lane; for Lambda <= 32 the partner value is lane e xor Lambda and comes
+//     through DPP / ds_swizzle / ds_bpermute.  The channel LLRs are stage n.
+//   * bit vectors (decided bits, partial sums) are one VGPR: lane w holds bits
+//     32w..32w+31.  The partial sums are kept "in place" (the N-bit beta array the paper
+//     adapts for FSSCS-RM in Section 4): after PL decided bits, each complete aligned
+//     block of the PL-prefix holds its own beta.
+//   * the stack: slot s is lane s (D <= 64), holding the path metric, a packed key,
+//     the length and an incremental CRC-16 register; the decided bits of slot s live in
+//     LDS row s.  Best / worst path = wave-wide min / max reductions (DPP), free slots and
+//     pruning = ballots.
+//   * a switch recomputes only the stages whose node differs between the path held in
+//     the tree and the new path (lowest common ancestor of the two leaves, and the first
+//     bit where their decisions differ); the values are identical to the paper's
+//     recompute from the root because every alpha is a function of the channel LLRs and
+//     the decided prefix only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "polar_code.h"
+#include "polarscs.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr uint32_t kSeqBits = 21;
+constexpr uint32_t kSeqMask = (1u << kSeqBits) - 1;
+
+// Kernel-argument copy of a code's tables.
+struct CodeArgs {
+  int32_t N, K, crc, logn, W, kp;
+  uint32_t info[64];
+  uint16_t pre[64];
+};
+
+CodeArgs make_args(const polar_code* c) {
+  CodeArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.N = c->N;
+  a.K = c->K;
+  a.crc = c->crc;
+  a.logn = c->logn;
+  a.W = c->words();
+  a.kp = c->payload_bits();
+  std::memcpy(a.info, c->info_words, sizeof a.info);
+  std::memcpy(a.pre, c->info_prefix, sizeof a.pre);
+  return a;
+}
+
+// ------------------------------------------------------------------------------------
+// Cross-lane primitives
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+// v from lane (lane xor M), M a power of two <= 32.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  if constexpr (M == 1) {
+    return dpp<0xB1>(v);  // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return dpp<0x4E>(v);  // quad_perm [2,3,0,1]
+  } else if constexpr (M <= 16) {
+    // ds_swizzle bit mode: and_mask = 0x1F, or_mask = 0, xor_mask = M
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (M << 10) | 0x1F);
+  } else {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ M) << 2, (int)v);
+  }
+}
+
+__device__ __forceinline__ uint32_t xor_lane_rt(uint32_t v, int m) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ m) << 2, (int)v);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Wave-wide unsigned min / max; every lane contributes.  Butterfly over quads, then
+// half-rows and rows by mirroring, then the four row results on the scalar unit.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+  v = min(v, dpp<0xB1>(v));
+  v = min(v, dpp<0x4E>(v));
+  v = min(v, dpp<0x141>(v));  // row_half_mirror
+  v = min(v, dpp<0x140>(v));  // row_mirror
+  return min(min(readlane(v, 0), readlane(v, 16)), min(readlane(v, 32), readlane(v, 48)));
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+  v = max(v, dpp<0xB1>(v));
+  v = max(v, dpp<0x4E>(v));
+  v = max(v, dpp<0x141>(v));
+  v = max(v, dpp<0x140>(v));
+  return max(max(readlane(v, 0), readlane(v, 16)), max(readlane(v, 32), readlane(v, 48)));
+}
+
+__device__ __forceinline__ int msb(uint32_t x) { return 31 - __builtin_clz(x); }
+
+// Bits [0, lim) of a lane-per-word bit vector.
+__device__ __forceinline__ uint32_t prefix_mask(int lane, int lim) {
+  const int lo = lane * 32;
+  if (lo + 32 <= lim) return 0xFFFFFFFFu;
+  if (lo >= lim) return 0u;
+  return (1u << (lim - lo)) - 1u;
+}
+
+// ------------------------------------------------------------------------------------
+// Arithmetic of the two precisions (values travel as 32-bit patterns).
+// ------------------------------------------------------------------------------------
+struct TrF32 {
+  typedef float In;
+  __device__ static __forceinline__ uint32_t load(const float* p, int64_t j) {
+    return __float_as_uint(p[j]);
+  }
+  // f = sign(a) sign(b) min(|a|, |b|), sign from the IEEE sign bits.
+  __device__ static __forceinline__ uint32_t f(uint32_t a, uint32_t b) {
+    const float m = fminf(fabsf(__uint_as_float(a)), fabsf(__uint_as_float(b)));
+    return __float_as_uint(m) | ((a ^ b) & 0x80000000u);
+  }
+  // g = b + (-1)^u a, one binary32 addition.
+  __device__ static __forceinline__ uint32_t g(uint32_t a, uint32_t b, bool u) {
+    const float fa = __uint_as_float(a);
+    return __float_as_uint(__uint_as_float(b) + (u ? -fa : fa));
+  }
+  __device__ static __forceinline__ bool hd(uint32_t a) { return __uint_as_float(a) < 0.0f; }
+  __device__ static __forceinline__ uint32_t mag(uint32_t a) { return a & 0x7FFFFFFFu; }
+  __device__ static __forceinline__ uint32_t pm_add(uint32_t pm, uint32_t m) {
+    return __float_as_uint(__uint_as_float(pm) + __uint_as_float(m));
+  }
+};
+
+struct TrI8 {
+  typedef int8_t In;
+  __device__ static __forceinline__ uint32_t load(const int8_t* p, int64_t j) {
+    const int v = p[j];
+    return (uint32_t)(v < -127 ? -127 : v);
+  }
+  __device__ static __forceinline__ uint32_t f(uint32_t a, uint32_t b) {
+    const int ia = (int)a, ib = (int)b;
+    const int m = min(abs(ia), abs(ib));
+    return (uint32_t)(((ia ^ ib) < 0) ? -m : m);
+  }
+  __device__ static __forceinline__ uint32_t g(uint32_t a, uint32_t b, bool u) {
+    const int s = (int)b + (u ? -(int)a : (int)a);
+    return (uint32_t)min(max(s, -127), 127);
+  }
+  __device__ static __forceinline__ bool hd(uint32_t a) { return (int)a < 0; }
+  __device__ static __forceinline__ uint32_t mag(uint32_t a) { return (uint32_t)abs((int)a); }
+  __device__ static __forceinline__ uint32_t pm_add(uint32_t pm, uint32_t m) {
+    return min(pm + m, 32767u);
+  }
+};
+
+// ------------------------------------------------------------------------------------
+// alpha tree layout
+// ------------------------------------------------------------------------------------
+template <int LOGN>
+struct Layout {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int regs(int lam) { return (1 << lam) > kWave ? (1 << lam) / kWave : 1; }
+  static constexpr int off(int lam) {
+    int s = 0;
+    for (int l = 0; l < lam; ++l) s += regs(l);
+    return s;
+  }
+  static constexpr int total = off(LOGN + 1);
+  static constexpr int W = N >= 32 ? N / 32 : 1;
+};
+
+// alpha of node (lambda, phi) from its parent (eq. llrcalc): f for even phi, g with the
+// partial sums of the left sibling block [base, base + Lambda) for odd phi.
+template <int LAM, int LOGN, class TR>
+__device__ __forceinline__ void stage(uint32_t (&a)[Layout<LOGN>::total], bool odd, int base,
+                                      uint32_t beta, int lane) {
+  using LY = Layout<LOGN>;
+  constexpr int LAMBDA = 1 << LAM;
+  constexpr int PO = LY::off(LAM + 1);
+  constexpr int VO = LY::off(LAM);
+  if constexpr (LAMBDA >= kWave) {
+    constexpr int R = LAMBDA / kWave;
+    if (!odd) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[VO + r] = TR::f(a[PO + r], a[PO + r + R]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int w0 = (base >> 5) + 2 * r;
+        const uint32_t lo = readlane(beta, w0);
+        const uint32_t hi = readlane(beta, w0 + 1);
+        const uint32_t m = lane < 32 ? lo : hi;
+        a[VO + r] = TR::g(a[PO + r], a[PO + r + R], (m >> (lane & 31)) & 1u);
+      }
+    }
+  } else {
+    const uint32_t p = a[PO];
+    const uint32_t q = xor_lane<LAMBDA>(p);
+    if (!odd) {
+      a[VO] = TR::f(p, q);
+    } else {
+      const uint32_t m = readlane(beta, base >> 5) >> (base & 31);
+      a[VO] = TR::g(p, q, (m >> (lane & 31)) & 1u);
+    }
+  }
+}
+
+template <int LAM, int LOGN, class TR>
+__device__ __forceinline__ void descend(uint32_t (&a)[Layout<LOGN>::total], int top, int i,
+                                        uint32_t beta, int lane, uint32_t& fg) {
+  if constexpr (LAM >= 0) {
+    if (LAM <= top) {
+      stage<LAM, LOGN, TR>(a, (i >> LAM) & 1, ((i >> LAM) - 1) << LAM, beta, lane);
+      fg += 1u << LAM;
+    }
+    descend<LAM - 1, LOGN, TR>(a, top, i, beta, lane, fg);
+  }
+}
+
+// In-place partial sums: write decided bit `bit` at position pos (the path had length pos)
+// and fold every block that this completes (eq. bitcalc: left half ^= right half).
+template <int LOGN>
+__device__ __forceinline__ uint32_t beta_push(uint32_t beta, int pos, uint32_t bit, int lane) {
+  const int w = pos >> 5;
+  uint32_t x = readlane(beta, w);
+  x = (x & ~(1u << (pos & 31))) | (bit << (pos & 31));
+  const int t = __builtin_ctz(~(uint32_t)pos);  // number of completed levels
+  const int tin = t < 5 ? t : 5;
+  for (int lam = 0; lam < tin; ++lam) {
+    const int half = 1 << lam;
+    const int start = ((pos >> (lam + 1)) << (lam + 1)) & 31;
+    x ^= (x >> half) & (((1u << half) - 1u) << start);
+  }
+  beta = (lane == w) ? x : beta;
+  if constexpr (LOGN > 5) {
+    for (int lam = 5; lam < t; ++lam) {
+      const int dw = 1 << (lam - 5);
+      const int a0 = (pos >> (lam + 1)) << (lam + 1 - 5);
+      const uint32_t y = xor_lane_rt(beta, dw);
+      if (lane >= a0 && lane < a0 + dw) beta ^= y;
+    }
+  }
+  return beta;
+}
+
+// In-place partial sums of the first PL bits of u, from scratch: butterfly stage s is
+// applied inside every complete aligned block of 2^(s+1) positions below PL.
+template <int LOGN>
+__device__ __forceinline__ uint32_t beta_build(uint32_t u, int PL, int lane) {
+  uint32_t x = u & prefix_mask(lane, PL);
+  constexpr uint32_t kLow[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
+                                0x0000FFFFu};
+#pragma unroll
+  for (int s = 0; s < (LOGN < 5 ? LOGN : 5); ++s) {
+    const int lim = (PL >> (s + 1)) << (s + 1);
+    x ^= (x >> (1 << s)) & kLow[s] & prefix_mask(lane, lim);
+  }
+#pragma unroll
+  for (int s = 5; s < LOGN; ++s) {
+    const int dw = 1 << (s - 5);
+    const int limw = (PL >> (s + 1)) << (s + 1 - 5);
+    const uint32_t y = xor_lane_rt(x, dw);
+    if (!(lane & dw) && lane < limw) x ^= y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t crc_step(uint32_t reg, uint32_t bit) {
+  const uint32_t top = ((reg >> 15) ^ bit) & 1u;
+  reg = (reg << 1) & 0xFFFFu;
+  return top ? (reg ^ 0x1021u) : reg;
+}
+
+__device__ __forceinline__ uint32_t key_lo(int N, int pl, uint32_t seq) {
+  const int d = N - pl;
+  return ((uint32_t)(d > 2047 ? 2047 : d) << kSeqBits) | (seq & kSeqMask);
+}
+
+struct FrameJob {
+  const void* llr;   // N values of the frame
+  uint8_t* payload;  // kp output bits
+  uint8_t* status;
+  scs_stats* stats;  // may be null
+  int D, L;
+};
+
+// One frame, one wavefront.  rows: D * W words of LDS, cnt: N bytes of LDS (the caller
+// provides both, private to this wave).
+template <int LOGN, class TR>
+__device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJob& job,
+                                             uint32_t* rows, uint32_t* cnt32) {
+  using LY = Layout<LOGN>;
+  constexpr int N = LY::N;
+  constexpr int W = LY::W;
+  const int lane = lane_id();
+  const int D = job.D, L = job.L;
+  const int crc_bits = code.crc;
+
+  // per-lane copies of the code tables (lane w: word w)
+  const uint32_t infow = lane < W ? code.info[lane] : 0u;
+
+  // clear the L counters
+  for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
+
+  // channel LLRs -> stage n (coalesced: register r takes values 64 r .. 64 r + 63)
+  uint32_t a[LY::total];
+#pragma unroll
+  for (int r = 0; r < LY::total; ++r) a[r] = 0u;
+  {
+    const typename TR::In* src = (const typename TR::In*)job.llr;
+    constexpr int RN = LY::regs(LOGN);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      const int e = r * kWave + lane;
+      if (e < N) a[LY::off(LOGN) + r] = TR::load(src, e);
+    }
+  }
+
+  // stack: slot s = lane s
+  uint32_t s_pm = 0u, s_lo = key_lo(N, 0, 0u), s_crc = 0u;
+  int s_pl = 0;
+  uint64_t vmask = 1ull;  // the empty path in slot 0
+  const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
+  uint32_t next_seq = 1;
+
+  // the path held in the tree
+  int wl = -1;                      // its length when alpha was last computed (-1: none)
+  uint32_t last_seq0 = 0xFFFFFFFFu;  // first child of the last extension
+  uint32_t ucur = 0u, beta = 0u;
+
+  uint32_t fb = 0u, out = 0u;
+  bool have_fb = false;
+  int fails = 0;
+  uint32_t st = 0u;
+  uint32_t n_it = 0, n_sw = 0, n_cp = 0, n_sc = 0, n_fg = 0, n_ev = 0, n_dr = 0, n_pr = 0;
+
+  const uint32_t cap = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
+  for (uint32_t guard = 0; guard < cap; ++guard) {
+    if (vmask == 0ull) {
+      st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
+      out = fb;
+      break;
+    }
+    // best path: min of (PM, N - PL, seq)
+    const bool live = (vmask >> lane) & 1ull;
+    const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
+    const uint32_t mh = wave_min(kh);
+    const uint64_t tie = ballot(kh == mh) & vmask;
+    int p;
+    if (__builtin_popcountll(tie) == 1) {
+      p = __builtin_ctzll(tie);
+    } else {
+      const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
+      const uint32_t ml = wave_min(kl);
+      p = __builtin_ctzll(ballot(kl == ml) & tie);
+    }
+    const int pl = (int)readlane((uint32_t)s_pl, p);
+    const uint32_t plo = readlane(s_lo, p);
+    const uint32_t ppm = readlane(s_pm, p);
+    const uint32_t pcrc = readlane(s_crc, p);
+    const uint32_t pseq = plo & kSeqMask;
+    vmask &= ~(1ull << p);
+
+    if (pl == N) {  // a complete path: CRC decides (Section 2.2.5)
+      ++n_cp;
+      const uint32_t row = lane < W ? rows[p * W + lane] : 0u;
+      if (crc_bits == 0 || pcrc == 0u) {
+        st = SCS_STATUS_OK;
+        out = row;
+        break;
+      }
+      if (!have_fb) {
+        fb = row;
+        have_fb = true;
+      }
+      if (++fails >= L) {
+        st = SCS_STATUS_FALLBACK;
+        out = fb;
+        break;
+      }
+      continue;
+    }
+
+    const int i = pl;
+    ++n_it;
+    n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
+
+    // bring the tree to path p at leaf i
+    int top;
+    if (pseq == last_seq0) {
+      // the first child of the last extension: the SC schedule continues
+      beta = beta_push<LOGN>(beta, wl, (readlane(ucur, wl >> 5) >> (wl & 31)) & 1u, lane);
+      top = __builtin_ctz((uint32_t)i);
+    } else {
+      ++n_sw;
+      const uint32_t nu = lane < W ? rows[p * W + lane] : 0u;
+      int A, d;
+      if (wl < 0) {
+        A = LOGN;
+        d = 0;
+      } else {
+        const int lim = wl < i ? wl : i;
+        const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
+        const uint64_t bx = ballot(x != 0u);
+        if (bx == 0ull) {
+          d = lim;
+        } else {
+          const int w = __builtin_ctzll(bx);
+          d = w * 32 + __builtin_ctz(readlane(x, w));
+        }
+        A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
+      }
+      const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
+      top = (A > Bm ? A : Bm) - 1;
+      if (wl >= 0 && i == wl + 1 && d >= wl)
+        beta = beta_push<LOGN>(beta, wl, (readlane(nu, wl >> 5) >> (wl & 31)) & 1u, lane);
+      else
+        beta = beta_build<LOGN>(nu, i, lane);
+      ucur = nu;
+    }
+    descend<LOGN - 1, LOGN, TR>(a, top, i, beta, lane, n_fg);
+    const uint32_t a0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a[LY::off(0)]);
+
+    // leaf decision and children (eq. scest, eq. PMupd)
+    const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
+    const bool h = TR::hd(a0);
+    const uint32_t mag = TR::mag(a0);
+    uint32_t b0, pm0, crc0;
+    if (info) {
+      b0 = h ? 1u : 0u;
+      pm0 = ppm;
+      crc0 = crc_step(pcrc, b0);
+    } else {
+      b0 = 0u;
+      pm0 = h ? TR::pm_add(ppm, mag) : ppm;
+      crc0 = pcrc;
+    }
+    const uint32_t seq0 = next_seq++;
+    const int wi = i >> 5;
+    const uint32_t bitm = 1u << (i & 31);
+    if (lane == wi) {
+      ucur = (ucur & ~bitm) | (b0 ? bitm : 0u);
+      rows[p * W + lane] = ucur;
+    }
+    if (lane == p) {
+      s_pm = pm0;
+      s_lo = key_lo(N, i + 1, seq0);
+      s_pl = i + 1;
+      s_crc = crc0;
+    }
+    vmask |= 1ull << p;
+
+    if (info) {
+      const uint32_t b1 = b0 ^ 1u;
+      const uint32_t pm1 = TR::pm_add(ppm, mag);
+      const uint32_t crc1 = crc_step(pcrc, b1);
+      const uint32_t seq1 = next_seq++;
+      const uint32_t lo1 = key_lo(N, i + 1, seq1);
+      int t = -1;
+      if (__builtin_popcountll(vmask) < D) {
+        t = __builtin_ctzll(~vmask & dmask);
+      } else {
+        const bool lv = (vmask >> lane) & 1ull;
+        const uint32_t xh = lv ? s_pm : 0u;
+        const uint32_t Mh = wave_max(xh);
+        const uint64_t tq = ballot(xh == Mh) & vmask;
+        int q;
+        if (__builtin_popcountll(tq) == 1) {
+          q = __builtin_ctzll(tq);
+        } else {
+          const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
+          const uint32_t Ml = wave_max(xl);
+          q = __builtin_ctzll(ballot(xl == Ml) & tq);
+        }
+        const uint32_t qh = readlane(s_pm, q), ql = readlane(s_lo, q);
+        if (pm1 < qh || (pm1 == qh && lo1 < ql)) {
+          t = q;
+          ++n_ev;
+        } else {
+          ++n_dr;
+        }
+      }
+      if (t >= 0) {
+        if (lane < W) rows[t * W + lane] = ucur ^ (lane == wi ? bitm : 0u);
+        if (lane == t) {
+          s_pm = pm1;
+          s_lo = lo1;
+          s_pl = i + 1;
+          s_crc = crc1;
+        }
+        vmask |= 1ull << t;
+      }
+    }
+
+    // L counter of length i
+    uint32_t old = 0u;
+    if (lane == 0) old = atomicAdd(&cnt32[i >> 2], 1u << (8 * (i & 3)));
+    old = readlane(old, 0);
+    if ((int)((old >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
+      ++n_pr;
+      vmask &= ~ballot(s_pl <= i);
+    }
+    wl = i;
+    last_seq0 = seq0;
+  }
+
+  // output: payload = the first K - r information bits of the output path
+  if (lane < W) {
+    uint32_t iw = infow;
+    int k = code.pre[lane];
+    uint8_t* dst = job.payload;
+    while (iw) {
+      const int b = __builtin_ctz(iw);
+      iw &= iw - 1u;
+      if (k < code.kp) dst[k] = (uint8_t)((st ? (out >> b) : 0u) & 1u);
+      ++k;
+    }
+  }
+  if (lane == 0) *job.status = (uint8_t)st;
+  if (job.stats) {
+    const uint32_t v[8] = {n_it, n_sw, n_cp, n_sc, n_fg, n_ev, n_dr, n_pr};
+    if (lane < 8) {
+      uint32_t x = v[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) x = lane == j ? v[j] : x;
+      reinterpret_cast<uint32_t*>(job.stats)[lane] = x;
+    }
+  }
+}
+
+// LDS words per wave: decided-bit rows and the per-length counters.
+inline int lds_words_per_wave(int N, int D) {
+  const int W = N >= 32 ? N / 32 : 1;
+  return D * W + (N + 3) / 4;
+}
+
+template <int LOGN, class TR>
+__global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, int L,
+                                                          const typename TR::In* __restrict__ llr,
+                                                          int64_t n_frames,
+                                                          uint8_t* __restrict__ payload,
+                                                          uint8_t* __restrict__ status,
+                                                          scs_stats* __restrict__ stats,
+                                                          int wave_words) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t frame = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (frame >= n_frames) return;
+  constexpr int N = 1 << LOGN;
+  constexpr int W = Layout<LOGN>::W;
+  uint32_t* rows = lds + wave * wave_words;
+  uint32_t* cnt = rows + D * W;
+  FrameJob job;
+  job.llr = llr + frame * N;
+  job.payload = payload + frame * code.kp;
+  job.status = status + frame;
+  job.stats = stats ? stats + frame : nullptr;
+  job.D = D;
+  job.L = L;
+  decode_frame<LOGN, TR>(code, job, rows, cnt);
+}
+
+// ------------------------------------------------------------------------------------
+// Device encoder: one wave per frame, lane w owns bits 32w..32w+31 of u.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void encode_kernel(CodeArgs code, const uint16_t* __restrict__ crc_unit,
+                                                     const uint8_t* __restrict__ payload,
+                                                     uint8_t* __restrict__ codeword, int64_t B) {
+  const int lane = lane_id();
+  const int64_t f = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (f >= B) return;
+  const uint8_t* pl = payload + f * code.kp;
+  // CRC remainder: xor of the remainders of the payload's one-bits (linear CRC)
+  uint32_t r = 0u;
+  if (code.crc) {
+    for (int k = lane; k < code.kp; k += kWave)
+      if (pl[k] & 1u) r ^= crc_unit[k];
+    for (int m = 1; m < kWave; m <<= 1) r ^= xor_lane_rt(r, m);
+  }
+  uint32_t x = 0u;
+  if (lane < code.W) {
+    uint32_t iw = code.info[lane];
+    int k = code.pre[lane];
+    while (iw) {
+      const int b = __builtin_ctz(iw);
+      iw &= iw - 1u;
+      uint32_t bit;
+      if (k < code.kp) bit = pl[k] & 1u;
+      else bit = (r >> (code.crc - 1 - (k - code.kp))) & 1u;
+      x |= bit << b;
+      ++k;
+    }
+  }
+  // u F^(x)n: in-word butterflies, then across words
+  constexpr uint32_t kLow[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu, 0x0000FFFFu};
+  for (int s = 0; s < 5 && (1 << s) < code.N; ++s) x ^= (x >> (1 << s)) & kLow[s];
+  for (int dw = 1; dw < code.W; dw <<= 1) {
+    const uint32_t y = xor_lane_rt(x, dw);
+    if (!(lane & dw)) x ^= y;
+  }
+  if (lane < code.W) {
+    uint8_t* dst = codeword + f * code.N + lane * 32;
+    const int nb = code.N < 32 ? code.N : 32;
+    for (int b = 0; b < nb; ++b) dst[b] = (uint8_t)((x >> b) & 1u);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------
+template <class TR>
+using UniformKernel = void (*)(CodeArgs, int, int, const typename TR::In*, int64_t, uint8_t*,
+                               uint8_t*, scs_stats*, int);
+
+template <class TR>
+UniformKernel<TR> uniform_kernel_for(int logn) {
+  switch (logn) {
+    case 1: return scs_uniform_kernel<1, TR>;
+    case 2: return scs_uniform_kernel<2, TR>;
+    case 3: return scs_uniform_kernel<3, TR>;
+    case 4: return scs_uniform_kernel<4, TR>;
+    case 5: return scs_uniform_kernel<5, TR>;
+    case 6: return scs_uniform_kernel<6, TR>;
+    case 7: return scs_uniform_kernel<7, TR>;
+    case 8: return scs_uniform_kernel<8, TR>;
+    case 9: return scs_uniform_kernel<9, TR>;
+    case 10: return scs_uniform_kernel<10, TR>;
+    case 11: return scs_uniform_kernel<11, TR>;
+  }
+  return nullptr;
+}
+
+int waves_per_block(int N, int D) {
+  const int bytes = lds_words_per_wave(N, D) * 4;
+  int wpb = 4;
+  while (wpb > 1 && wpb * bytes > 64 * 1024) wpb >>= 1;
+  return wpb;
+}
+
+}  // namespace
+
+struct scs_ctx {
+  int device = 0;
+  int last_error = POLAR_OK;
+  std::mutex mu;
+};
+
+extern "C" {
+
+int scs_ctx_create(int device, scs_ctx** out) {
+  if (!out) return POLAR_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return POLAR_EDEVICE;
+  if (device < 0 || device >= n) return POLAR_EINVAL;
+  scs_ctx* c = new (std::nothrow) scs_ctx;
+  if (!c) return POLAR_ENOMEM;
+  c->device = device;
+  *out = c;
+  return POLAR_OK;
+}
+
+void scs_ctx_destroy(scs_ctx* ctx) { delete ctx; }
+
+int scs_ctx_last_error(scs_ctx* ctx) {
+  if (!ctx) return POLAR_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  const int e = ctx->last_error;
+  ctx->last_error = POLAR_OK;
+  return e;
+}
+
+int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
+                     int32_t llr_dtype, const void* llr_dev, int64_t n_frames,
+                     uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
+                     void* hip_stream) {
+  if (!ctx || !code) return POLAR_EINVAL;
+  if (D < 1 || D > 64 || L < 1 || L > 255) return POLAR_EINVAL;
+  if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
+  if (n_frames < 0) return POLAR_EINVAL;
+  if (n_frames == 0) return POLAR_OK;
+  if (!llr_dev || !status_dev || (!payload_dev && code->payload_bits() > 0)) return POLAR_EINVAL;
+  if (code->logn < 1 || code->logn > 11) return POLAR_EUNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
+
+  const CodeArgs args = make_args(code);
+  const int wpb = waves_per_block(code->N, D);
+  const int wave_words = lds_words_per_wave(code->N, D);
+  const size_t lds = (size_t)wpb * wave_words * 4;
+  const int64_t blocks = (n_frames + wpb - 1) / wpb;
+  if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (llr_dtype == SCS_LLR_F32) {
+    auto k = uniform_kernel_for<TrF32>(code->logn);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
+                       (const float*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
+                       wave_words);
+  } else {
+    auto k = uniform_kernel_for<TrI8>(code->logn);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
+                       (const int8_t*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
+                       wave_words);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->last_error = POLAR_EDEVICE;
+    return POLAR_EDEVICE;
+  }
+  return POLAR_OK;
+}
+
+int scs_decode_mixed(scs_ctx*, const polar_code* const*, int32_t, const scs_frame*, int64_t,
+                     int32_t, const void*, uint8_t*, uint8_t*, scs_stats*, void*) {
+  return POLAR_EUNSUPPORTED;
+}
+
+int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
+                        uint8_t* codeword_dev, int64_t B, void* hip_stream) {
+  if (!code || B < 0) return POLAR_EINVAL;
+  if (B == 0) return POLAR_OK;
+  if (!codeword_dev || (!payload_dev && code->payload_bits() > 0)) return POLAR_EINVAL;
+  // The CRC unit table rides in a small device buffer owned per code and device.
+  static std::mutex mu;
+  static std::unordered_map<uint64_t, uint16_t*> tables;  // key: uid * 64 + device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EDEVICE;
+  uint16_t* tab = nullptr;
+  if (code->crc) {
+    std::lock_guard<std::mutex> g(mu);
+    const uint64_t key = code->uid * 64 + (uint64_t)dev;
+    auto it = tables.find(key);
+    if (it == tables.end()) {
+      const size_t bytes = sizeof(uint16_t) * (size_t)std::max(1, code->payload_bits());
+      if (hipMalloc(&tab, bytes) != hipSuccess) return POLAR_ENOMEM;
+      if (hipMemcpy(tab, code->crc_unit.data(), sizeof(uint16_t) * code->crc_unit.size(),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return POLAR_EDEVICE;
+      tables[key] = tab;
+    } else {
+      tab = it->second;
+    }
+  }
+  const CodeArgs args = make_args(code);
+  const int64_t blocks = (B + 3) / 4;
+  if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
+  hipLaunchKernelGGL(encode_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     args, (const uint16_t*)tab, payload_dev, codeword_dev, B);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EDEVICE;
+}
+
+}  // extern "C"

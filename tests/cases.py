@@ -1,0 +1,70 @@
+"""Seeded test cases shared by the parity tests: frames are encoded by the oracle's
+encoder (never by the library under test) and passed through the channel generator."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+import oracle
+from paper_1809_03606_amd import channel
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def make_frames(N, K, crc, ebn0, B, seed, stream=0, design_db=2.0, dtype="f32", scale=8.0):
+    info = oracle.construct(N, K, design_db)
+    pay = channel.payload_bits(seed, stream, 0, B, K - crc)
+    cw = oracle.encode_batch(info, crc, pay)
+    nz = channel.noise(seed, stream, 0, B, N)
+    if dtype == "f32":
+        llr = channel.bpsk_awgn_llr(cw, nz, ebn0, K / N)
+    else:
+        llr = channel.bpsk_awgn_i8(cw, nz, ebn0, K / N, scale)
+    return info, pay, llr
+
+
+def oracle_decode(info, crc, D, L, llr):
+    mode = oracle.F32 if llr.dtype == np.float32 else oracle.FIX
+    return oracle.scs_decode_batch(mode, info, crc, D, L, llr, threads=THREADS)
+
+
+def gpu_decode(torch, code, D, L, llr, with_stats=True, ctx=None):
+    from paper_1809_03606_amd import binding
+
+    B = llr.shape[0]
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(np.ascontiguousarray(llr)).to(dev)
+    pay = torch.full((max(B, 1), code.payload_bits), 0xEE, dtype=torch.uint8, device=dev)
+    st = torch.full((max(B, 1),), 0xEE, dtype=torch.uint8, device=dev)
+    stats = torch.zeros((max(B, 1), 8), dtype=torch.int32, device=dev) if with_stats else None
+    own = ctx is None
+    if own:
+        ctx = binding.ScsContext(0)
+    ctx.decode(code, D, L, x, pay, st, stats)
+    torch.cuda.synchronize()
+    out = (pay[:B].cpu().numpy(), st[:B].cpu().numpy(),
+           stats[:B].cpu().numpy().view(np.uint32) if with_stats else None)
+    if own:
+        ctx.close()
+    return out
+
+
+CMP_STATS = ("iterations", "switches", "completions", "sc_elems", "evictions", "drops", "prunes")
+
+
+def assert_parity(gpu, ref, label=""):
+    gp, gs, gstats = gpu
+    rp, rs, rstats = ref
+    bad = np.nonzero((gp != rp).any(axis=1) | (gs != rs))[0]
+    assert bad.size == 0, "%s: %d frames differ, first %s (status gpu %s oracle %s)" % (
+        label, bad.size, bad[:8], gs[bad[:8]], rs[bad[:8]])
+    if gstats is not None:
+        from paper_1809_03606_amd.binding import STATS_FIELDS
+
+        for name in CMP_STATS:
+            g = gstats[:, STATS_FIELDS.index(name)].astype(np.uint64)
+            r = rstats[name]
+            d = np.nonzero(g != r)[0]
+            assert d.size == 0, "%s: stat %s differs on %d frames, first %d: gpu %d oracle %d" % (
+                label, name, d.size, d[0], g[d[0]], r[d[0]])
