@@ -173,67 +173,100 @@ struct TrI8 {
 };
 
 // ------------------------------------------------------------------------------------
-// alpha tree layout
+// alpha tree in LDS: stage lambda (Lambda = 2^lambda values) at word offset Lambda - 1,
+// stages 0 .. n-1 (N - 1 words); the channel LLRs (stage n) are read from the input.
 // ------------------------------------------------------------------------------------
 template <int LOGN>
 struct Layout {
   static constexpr int N = 1 << LOGN;
-  static constexpr int regs(int lam) { return (1 << lam) > kWave ? (1 << lam) / kWave : 1; }
-  static constexpr int off(int lam) {
-    int s = 0;
-    for (int l = 0; l < lam; ++l) s += regs(l);
-    return s;
-  }
-  static constexpr int total = off(LOGN + 1);
-  static constexpr int W = N >= 32 ? N / 32 : 1;
+  static constexpr int W = N >= 32 ? N / 32 : 1;     // 32-bit words per bit vector
+  static constexpr int SMALL = LOGN < 6 ? LOGN - 1 : 5;  // highest stage kept lane-parallel
 };
 
-// alpha of node (lambda, phi) from its parent (eq. llrcalc): f for even phi, g with the
-// partial sums of the left sibling block [base, base + Lambda) for odd phi.
+// Order LDS accesses of different lanes: the wave's LDS operations execute in issue
+// order, so only the compiler has to be kept from reordering them.
+__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Stage LAM >= 6 (Lambda >= 64), then the stages below it down to 6: value e = 64 r + lane
+// of stage lambda from values e and e + Lambda of its parent (eq. llrcalc): f for even
+// phi = i >> lambda, g for odd phi with the partial sums of the left sibling block.
 template <int LAM, int LOGN, class TR>
-__device__ __forceinline__ void stage(uint32_t (&a)[Layout<LOGN>::total], bool odd, int base,
-                                      uint32_t beta, int lane) {
-  using LY = Layout<LOGN>;
-  constexpr int LAMBDA = 1 << LAM;
-  constexpr int PO = LY::off(LAM + 1);
-  constexpr int VO = LY::off(LAM);
-  if constexpr (LAMBDA >= kWave) {
-    constexpr int R = LAMBDA / kWave;
-    if (!odd) {
+__device__ __forceinline__ void big_stages(int top, int i, uint32_t beta,
+                                           const typename TR::In* __restrict__ root,
+                                           uint32_t* al, int lane, uint32_t& fg) {
+  if constexpr (LAM >= 6) {
+    if (LAM <= top) {
+      constexpr int Lam = 1 << LAM;
+      const bool odd = (i >> LAM) & 1;
+      const int bw = ((((i >> LAM) - 1) << LAM) >> 5) + (lane >> 5);
+      uint32_t* dst = al + (Lam - 1);
+      const uint32_t* src = al + (2 * Lam - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[VO + r] = TR::f(a[PO + r], a[PO + r + R]);
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int w0 = (base >> 5) + 2 * r;
-        const uint32_t lo = readlane(beta, w0);
-        const uint32_t hi = readlane(beta, w0 + 1);
-        const uint32_t m = lane < 32 ? lo : hi;
-        a[VO + r] = TR::g(a[PO + r], a[PO + r + R], (m >> (lane & 31)) & 1u);
+      for (int r = 0; r < Lam / kWave; ++r) {
+        const int e = r * kWave + lane;
+        uint32_t pa, pb;
+        if constexpr (LAM + 1 == LOGN) {
+          pa = TR::load(root, e);
+          pb = TR::load(root, e + Lam);
+        } else {
+          pa = src[e];
+          pb = src[e + Lam];
+        }
+        uint32_t v;
+        if (!odd) {
+          v = TR::f(pa, pb);
+        } else {
+          const uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((bw + 2 * r) << 2, (int)beta);
+          v = TR::g(pa, pb, (w >> (lane & 31)) & 1u);
+        }
+        dst[e] = v;
       }
+      fg += (uint32_t)Lam;
+      lds_order();
     }
-  } else {
-    const uint32_t p = a[PO];
-    const uint32_t q = xor_lane<LAMBDA>(p);
-    if (!odd) {
-      a[VO] = TR::f(p, q);
-    } else {
-      const uint32_t m = readlane(beta, base >> 5) >> (base & 31);
-      a[VO] = TR::g(p, q, (m >> (lane & 31)) & 1u);
-    }
+    big_stages<LAM - 1, LOGN, TR>(top, i, beta, root, al, lane, fg);
   }
 }
 
 template <int LAM, int LOGN, class TR>
-__device__ __forceinline__ void descend(uint32_t (&a)[Layout<LOGN>::total], int top, int i,
-                                        uint32_t beta, int lane, uint32_t& fg) {
+__device__ __forceinline__ void small_chain(uint32_t& x, int start, int i, uint32_t beta,
+                                            uint32_t* al, int lane, uint32_t& fg) {
   if constexpr (LAM >= 0) {
-    if (LAM <= top) {
-      stage<LAM, LOGN, TR>(a, (i >> LAM) & 1, ((i >> LAM) - 1) << LAM, beta, lane);
+    if (LAM <= start) {
+      const uint32_t y = xor_lane<(1 << LAM)>(x);
+      if (((i >> LAM) & 1) == 0) {
+        x = TR::f(x, y);
+      } else {
+        const int base = ((i >> LAM) - 1) << LAM;
+        const uint32_t m = readlane(beta, base >> 5) >> (base & 31);
+        x = TR::g(x, y, (m >> (lane & 31)) & 1u);
+      }
+      if (lane < (1 << LAM)) al[(1 << LAM) - 1 + lane] = x;
       fg += 1u << LAM;
     }
-    descend<LAM - 1, LOGN, TR>(a, top, i, beta, lane, fg);
+    small_chain<LAM - 1, LOGN, TR>(x, start, i, beta, al, lane, fg);
   }
+}
+
+// Stages min(top, SMALL) .. 0 in one register (value e in lane e, partner in lane
+// e xor Lambda); every computed stage is stored for later leaves.  Returns the leaf LLR.
+template <int LOGN, class TR>
+__device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t beta,
+                                                 const typename TR::In* __restrict__ root,
+                                                 uint32_t* al, int lane, uint32_t& fg) {
+  constexpr int SM = Layout<LOGN>::SMALL;
+  const int start = top < SM ? top : SM;
+  if (start < 0) return (uint32_t)__builtin_amdgcn_readfirstlane((int)al[0]);
+  uint32_t x = 0u;
+  const int nin = 2 << start;  // values of stage start + 1
+  if (start + 1 == LOGN) {
+    if (lane < nin) x = TR::load(root, lane);
+  } else {
+    if (lane < nin) x = al[nin - 1 + lane];
+  }
+  small_chain<SM, LOGN, TR>(x, start, i, beta, al, lane, fg);
+  lds_order();
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
 // In-place partial sums: write decided bit `bit` at position pos (the path had length pos)
@@ -295,6 +328,10 @@ __device__ __forceinline__ uint32_t key_lo(int N, int pl, uint32_t seq) {
   return ((uint32_t)(d > 2047 ? 2047 : d) << kSeqBits) | (seq & kSeqMask);
 }
 
+__device__ __forceinline__ bool key_less(uint32_t ah, uint32_t al_, uint32_t bh, uint32_t bl) {
+  return ah < bh || (ah == bh && al_ < bl);
+}
+
 struct FrameJob {
   const void* llr;   // N values of the frame
   uint8_t* payload;  // kp output bits
@@ -303,37 +340,31 @@ struct FrameJob {
   int D, L;
 };
 
-// One frame, one wavefront.  rows: D * W words of LDS, cnt: N bytes of LDS (the caller
-// provides both, private to this wave).
+// LDS words per wave: decided-bit rows, per-length counters, alpha tree.
+inline int lds_words_per_wave(int N, int D) {
+  const int W = N >= 32 ? N / 32 : 1;
+  return D * W + (N + 3) / 4 + N;
+}
+
+// One frame, one wavefront.  `lds` is this wave's private region of
+// lds_words_per_wave(N, D) words.
 template <int LOGN, class TR>
 __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJob& job,
-                                             uint32_t* rows, uint32_t* cnt32) {
+                                             uint32_t* lds) {
   using LY = Layout<LOGN>;
   constexpr int N = LY::N;
   constexpr int W = LY::W;
   const int lane = lane_id();
   const int D = job.D, L = job.L;
   const int crc_bits = code.crc;
+  const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
+  uint32_t* rows = lds;                       // D x W words: decided bits of slot s in row s
+  uint32_t* cnt32 = lds + D * W;              // N bytes: extensions per length
+  uint32_t* al = cnt32 + (N + 3) / 4;         // N - 1 words: alpha stages 0 .. n-1
 
-  // per-lane copies of the code tables (lane w: word w)
   const uint32_t infow = lane < W ? code.info[lane] : 0u;
-
-  // clear the L counters
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
-
-  // channel LLRs -> stage n (coalesced: register r takes values 64 r .. 64 r + 63)
-  uint32_t a[LY::total];
-#pragma unroll
-  for (int r = 0; r < LY::total; ++r) a[r] = 0u;
-  {
-    const typename TR::In* src = (const typename TR::In*)job.llr;
-    constexpr int RN = LY::regs(LOGN);
-#pragma unroll
-    for (int r = 0; r < RN; ++r) {
-      const int e = r * kWave + lane;
-      if (e < N) a[LY::off(LOGN) + r] = TR::load(src, e);
-    }
-  }
+  lds_order();
 
   // stack: slot s = lane s
   uint32_t s_pm = 0u, s_lo = key_lo(N, 0, 0u), s_crc = 0u;
@@ -342,9 +373,19 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
   uint32_t next_seq = 1;
 
+  // fast path: the first child of the last extension ("candidate") wins whenever its key
+  // is below a lower bound on every other live key
+  bool have_cand = false;
+  int cand_slot = 0, cand_pl = 0;
+  uint32_t cand_hi = 0u, cand_lo = 0u, cand_crc = 0u;
+  uint32_t lb_hi = 0u, lb_lo = 0u;
+  // exact worst live key, when known
+  bool have_max = false;
+  int max_slot = 0;
+  uint32_t max_hi = 0u, max_lo = 0u;
+
   // the path held in the tree
-  int wl = -1;                      // its length when alpha was last computed (-1: none)
-  uint32_t last_seq0 = 0xFFFFFFFFu;  // first child of the last extension
+  int wl = -1;
   uint32_t ucur = 0u, beta = 0u;
 
   uint32_t fb = 0u, out = 0u;
@@ -354,31 +395,55 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   uint32_t n_it = 0, n_sw = 0, n_cp = 0, n_sc = 0, n_fg = 0, n_ev = 0, n_dr = 0, n_pr = 0;
 
   const uint32_t cap = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
-  for (uint32_t guard = 0; guard < cap; ++guard) {
+  bool done = false;
+  for (uint32_t guard = 0; !done && guard < cap; ++guard) {
     if (vmask == 0ull) {
       st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
       out = fb;
+      done = true;
       break;
     }
-    // best path: min of (PM, N - PL, seq)
-    const bool live = (vmask >> lane) & 1ull;
-    const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
-    const uint32_t mh = wave_min(kh);
-    const uint64_t tie = ballot(kh == mh) & vmask;
-    int p;
-    if (__builtin_popcountll(tie) == 1) {
-      p = __builtin_ctzll(tie);
+    // ---- the best path -------------------------------------------------------------
+    int p, pl;
+    uint32_t ppm, plo, pcrc;
+    bool cont;
+    if (have_cand && key_less(cand_hi, cand_lo, lb_hi, lb_lo)) {
+      p = cand_slot;
+      pl = cand_pl;
+      ppm = cand_hi;
+      plo = cand_lo;
+      pcrc = cand_crc;
+      cont = true;
     } else {
-      const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
-      const uint32_t ml = wave_min(kl);
-      p = __builtin_ctzll(ballot(kl == ml) & tie);
+      const bool live = (vmask >> lane) & 1ull;
+      const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
+      const uint32_t mh = wave_min(kh);
+      const uint64_t tie = ballot(kh == mh) & vmask;
+      if (__builtin_popcountll(tie) == 1) {
+        p = __builtin_ctzll(tie);
+      } else {
+        const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
+        const uint32_t ml = wave_min(kl);
+        p = __builtin_ctzll(ballot(kl == ml) & tie);
+      }
+      pl = (int)readlane((uint32_t)s_pl, p);
+      plo = readlane(s_lo, p);
+      ppm = mh;
+      pcrc = readlane(s_crc, p);
+      cont = have_cand && p == cand_slot && plo == cand_lo;
+      // lower bound on the keys that stay after p is taken
+      if (__builtin_popcountll(tie) > 1) {
+        lb_hi = mh;
+        lb_lo = 0u;
+      } else {
+        const uint32_t k2 = (live && lane != p) ? s_pm : 0xFFFFFFFFu;
+        lb_hi = wave_min(k2);
+        lb_lo = 0u;
+      }
     }
-    const int pl = (int)readlane((uint32_t)s_pl, p);
-    const uint32_t plo = readlane(s_lo, p);
-    const uint32_t ppm = readlane(s_pm, p);
-    const uint32_t pcrc = readlane(s_crc, p);
-    const uint32_t pseq = plo & kSeqMask;
     vmask &= ~(1ull << p);
+    if (have_max && max_slot == p) have_max = false;
+    have_cand = false;
 
     if (pl == N) {  // a complete path: CRC decides (Section 2.2.5)
       ++n_cp;
@@ -386,16 +451,17 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       if (crc_bits == 0 || pcrc == 0u) {
         st = SCS_STATUS_OK;
         out = row;
-        break;
-      }
-      if (!have_fb) {
-        fb = row;
-        have_fb = true;
-      }
-      if (++fails >= L) {
-        st = SCS_STATUS_FALLBACK;
-        out = fb;
-        break;
+        done = true;
+      } else {
+        if (!have_fb) {
+          fb = row;
+          have_fb = true;
+        }
+        if (++fails >= L) {
+          st = SCS_STATUS_FALLBACK;
+          out = fb;
+          done = true;
+        }
       }
       continue;
     }
@@ -403,10 +469,13 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     const int i = pl;
     ++n_it;
     n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
+    // L counter of length i (result needed at the end of the iteration)
+    uint32_t old = 0u;
+    if (lane == 0) old = atomicAdd(&cnt32[i >> 2], 1u << (8 * (i & 3)));
 
-    // bring the tree to path p at leaf i
+    // ---- bring the tree to path p at leaf i ---------------------------------------
     int top;
-    if (pseq == last_seq0) {
+    if (cont) {
       // the first child of the last extension: the SC schedule continues
       beta = beta_push<LOGN>(beta, wl, (readlane(ucur, wl >> 5) >> (wl & 31)) & 1u, lane);
       top = __builtin_ctz((uint32_t)i);
@@ -437,10 +506,10 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
         beta = beta_build<LOGN>(nu, i, lane);
       ucur = nu;
     }
-    descend<LOGN - 1, LOGN, TR>(a, top, i, beta, lane, n_fg);
-    const uint32_t a0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a[LY::off(0)]);
+    if (top >= 6) big_stages<LOGN - 1, LOGN, TR>(top, i, beta, root, al, lane, n_fg);
+    const uint32_t a0 = small_stages<LOGN, TR>(top, i, beta, root, al, lane, n_fg);
 
-    // leaf decision and children (eq. scest, eq. PMupd)
+    // ---- leaf decision and children (eq. scest, eq. PMupd) -------------------------
     const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
     const bool h = TR::hd(a0);
     const uint32_t mag = TR::mag(a0);
@@ -455,6 +524,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       crc0 = pcrc;
     }
     const uint32_t seq0 = next_seq++;
+    const uint32_t lo0 = key_lo(N, i + 1, seq0);
     const int wi = i >> 5;
     const uint32_t bitm = 1u << (i & 31);
     if (lane == wi) {
@@ -463,11 +533,16 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     }
     if (lane == p) {
       s_pm = pm0;
-      s_lo = key_lo(N, i + 1, seq0);
+      s_lo = lo0;
       s_pl = i + 1;
       s_crc = crc0;
     }
     vmask |= 1ull << p;
+    if (have_max && key_less(max_hi, max_lo, pm0, lo0)) {
+      max_hi = pm0;
+      max_lo = lo0;
+      max_slot = p;
+    }
 
     if (info) {
       const uint32_t b1 = b0 ^ 1u;
@@ -478,22 +553,33 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       int t = -1;
       if (__builtin_popcountll(vmask) < D) {
         t = __builtin_ctzll(~vmask & dmask);
-      } else {
-        const bool lv = (vmask >> lane) & 1ull;
-        const uint32_t xh = lv ? s_pm : 0u;
-        const uint32_t Mh = wave_max(xh);
-        const uint64_t tq = ballot(xh == Mh) & vmask;
-        int q;
-        if (__builtin_popcountll(tq) == 1) {
-          q = __builtin_ctzll(tq);
-        } else {
-          const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
-          const uint32_t Ml = wave_max(xl);
-          q = __builtin_ctzll(ballot(xl == Ml) & tq);
+        if (have_max && key_less(max_hi, max_lo, pm1, lo1)) {
+          max_hi = pm1;
+          max_lo = lo1;
+          max_slot = t;
         }
-        const uint32_t qh = readlane(s_pm, q), ql = readlane(s_lo, q);
-        if (pm1 < qh || (pm1 == qh && lo1 < ql)) {
-          t = q;
+      } else {
+        if (!have_max) {
+          const bool lv = (vmask >> lane) & 1ull;
+          const uint32_t xh = lv ? s_pm : 0u;
+          const uint32_t Mh = wave_max(xh);
+          const uint64_t tq = ballot(xh == Mh) & vmask;
+          int q;
+          if (__builtin_popcountll(tq) == 1) {
+            q = __builtin_ctzll(tq);
+          } else {
+            const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
+            const uint32_t Ml = wave_max(xl);
+            q = __builtin_ctzll(ballot(xl == Ml) & tq);
+          }
+          max_slot = q;
+          max_hi = Mh;
+          max_lo = readlane(s_lo, q);
+          have_max = true;
+        }
+        if (key_less(pm1, lo1, max_hi, max_lo)) {
+          t = max_slot;
+          have_max = false;
           ++n_ev;
         } else {
           ++n_dr;
@@ -508,19 +594,28 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
           s_crc = crc1;
         }
         vmask |= 1ull << t;
+        if (key_less(pm1, lo1, lb_hi, lb_lo)) {
+          lb_hi = pm1;
+          lb_lo = lo1;
+        }
       }
     }
+    lds_order();
 
-    // L counter of length i
-    uint32_t old = 0u;
-    if (lane == 0) old = atomicAdd(&cnt32[i >> 2], 1u << (8 * (i & 3)));
+    // L-counter pruning
     old = readlane(old, 0);
     if ((int)((old >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
       ++n_pr;
       vmask &= ~ballot(s_pl <= i);
+      have_max = false;
     }
     wl = i;
-    last_seq0 = seq0;
+    have_cand = true;
+    cand_slot = p;
+    cand_pl = i + 1;
+    cand_hi = pm0;
+    cand_lo = lo0;
+    cand_crc = crc0;
   }
 
   // output: payload = the first K - r information bits of the output path
@@ -547,12 +642,6 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   }
 }
 
-// LDS words per wave: decided-bit rows and the per-length counters.
-inline int lds_words_per_wave(int N, int D) {
-  const int W = N >= 32 ? N / 32 : 1;
-  return D * W + (N + 3) / 4;
-}
-
 template <int LOGN, class TR>
 __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, int L,
                                                           const typename TR::In* __restrict__ llr,
@@ -566,9 +655,6 @@ __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, 
   const int64_t frame = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (frame >= n_frames) return;
   constexpr int N = 1 << LOGN;
-  constexpr int W = Layout<LOGN>::W;
-  uint32_t* rows = lds + wave * wave_words;
-  uint32_t* cnt = rows + D * W;
   FrameJob job;
   job.llr = llr + frame * N;
   job.payload = payload + frame * code.kp;
@@ -576,7 +662,7 @@ __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, 
   job.stats = stats ? stats + frame : nullptr;
   job.D = D;
   job.L = L;
-  decode_frame<LOGN, TR>(code, job, rows, cnt);
+  decode_frame<LOGN, TR>(code, job, lds + wave * wave_words);
 }
 
 // ------------------------------------------------------------------------------------

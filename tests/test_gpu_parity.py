@@ -83,7 +83,7 @@ def test_gpu_fixed_point_saturation(cuda):
     """Large quantiser scale: channel values clip at +-127 and g saturates often."""
     from paper_1809_03606_amd.binding import PolarCode
 
-    info, pay, llr = make_frames(256, 128, 16, 1.0, 101, seed=5, dtype="i8", scale=60.0)
+    info, pay, llr = make_frames(256, 128, 16, 1.0, 101, seed=5, dtype="i8", scale=100.0)
     assert (np.abs(llr.astype(int)) == 127).mean() > 0.2
     code = PolarCode(256, 128, 16, 2.0)
     ref = oracle_decode(info, 16, 16, 8, llr)
