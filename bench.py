@@ -55,11 +55,57 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2000,
                     help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
+    ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
+                    help="lanes per frame (0: the library's choice)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
+                  "paper_1809_03606_amd/csrc/scs_rows.hip")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(frames_per_launch: int):
+    """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE counters, or None when
+    the record is missing or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_frame"] * frames_per_launch
+
+
+def calibrate_copy(nbytes: int):
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}))
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
               "independent, see the design notes for how the batch would shard)" % args.gpus,
@@ -78,7 +124,7 @@ def main():
     kp = K - CRC
 
     code = binding.PolarCode(N, K, CRC, 2.0)
-    ctx = binding.ScsContext(0)
+    ctx = binding.ScsContext(0, args.lanes)
     stream = torch.cuda.Stream(device=dev)
     llr_dtype = binding.SCS_LLR_F32 if args.dtype == "f32" else binding.SCS_LLR_I8
 
@@ -176,7 +222,7 @@ def main():
     achieved = ops_per_launch / mean_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": measured_traffic(B),
                 "kernel": "scs_uniform_kernel<10,f32>" if args.dtype == "f32" else
                           "scs_uniform_kernel<10,i8>",
                 "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch}

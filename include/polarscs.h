@@ -91,6 +91,12 @@ typedef struct scs_ctx scs_ctx; /* per-device decoder context */
 int scs_ctx_create(int device, scs_ctx** out);
 void scs_ctx_destroy(scs_ctx* ctx);
 
+/* Lanes of a 64-lane wavefront given to one frame: 16 or 32 (several frames share a
+ * wavefront and its vector instructions) or 64 (one frame per wavefront); 0 lets the
+ * library choose (64; 16 and 32 fall back to 64 when their LDS state would not fit).  Results do
+ * not depend on this setting.  Errors: POLAR_EINVAL for any other value. */
+int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame);
+
 /* Per-frame counters (optional output of the decoders), one record per frame. */
 typedef struct {
   uint32_t iterations;  /* leaf estimates (path extensions) */

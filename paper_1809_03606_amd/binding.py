@@ -24,7 +24,7 @@ SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
-           "scs_decode_mixed", "scs_ctx_last_error", "polar_strerror")
+           "scs_decode_mixed", "scs_ctx_set_lanes", "scs_ctx_last_error", "polar_strerror")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
                 "drops", "prunes")
@@ -75,11 +75,12 @@ def lib():
             L.scs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
             L.scs_decode_mixed.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
+            L.scs_ctx_set_lanes.argtypes = [vp, i32]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
-                      "scs_ctx_last_error"):
+                      "scs_ctx_set_lanes", "scs_ctx_last_error"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -177,6 +178,10 @@ def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_de
                                   _addr(stats_dev), _stream(stream)), "scs_decode_mixed")
 
 
+def scs_ctx_set_lanes(ctx: int, lanes_per_frame: int):
+    _check(lib().scs_ctx_set_lanes(ctx, int(lanes_per_frame)), "scs_ctx_set_lanes")
+
+
 def scs_ctx_last_error(ctx: int) -> int:
     return int(lib().scs_ctx_last_error(ctx))
 
@@ -221,9 +226,11 @@ class PolarCode:
 
 
 class ScsContext:
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, lanes_per_frame: int = 0):
         self.handle = scs_ctx_create(device)
         self.device = device
+        if lanes_per_frame:
+            scs_ctx_set_lanes(self.handle, lanes_per_frame)
 
     def decode(self, code: PolarCode, D: int, L: int, llr_dev, payload_dev, status_dev,
                stats_dev=None, stream=None):

@@ -1,0 +1,28 @@
+// Host-side launch description shared between the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "scs_device.h"
+
+namespace polarscs {
+
+struct RowsLaunch {
+  CodeArgs code;
+  int G;                // lanes per frame: 16 or 32
+  int D, L, dtype;
+  int waves_per_block;
+  const void* llr;
+  int64_t n_frames;
+  uint8_t* payload;
+  uint8_t* status;
+  scs_stats* stats;
+  hipStream_t stream;
+};
+
+// LDS bytes of one workgroup of the several-frames-per-wavefront kernel.
+size_t rows_lds_bytes(int N, int D, int G, int waves_per_block);
+// Enqueue the several-frames-per-wavefront decoder.
+hipError_t launch_rows(const RowsLaunch& a);
+
+}  // namespace polarscs

@@ -19,17 +19,20 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run(cuda, N, K, crc, D, L, ebn0, B, seed, dtype="f32", label=None):
+LANES = [16, 32, 64]
+
+
+def _run(cuda, N, K, crc, D, L, ebn0, B, seed, dtype="f32", label=None, lanes=0):
     from paper_1809_03606_amd.binding import PolarCode
 
-    label = label or "N=%d K=%d crc=%d D=%d L=%d Eb/N0=%.1f B=%d seed=%d %s" % (
-        N, K, crc, D, L, ebn0, B, seed, dtype)
+    label = (label or "N=%d K=%d crc=%d D=%d L=%d Eb/N0=%.1f B=%d seed=%d %s" % (
+        N, K, crc, D, L, ebn0, B, seed, dtype)) + " lanes=%d" % lanes
     info, pay, llr = make_frames(N, K, crc, ebn0, B, seed, dtype=dtype)
     code = PolarCode(N, K, crc, 2.0)
     assert (code.info_mask == info).all()
     ref = oracle_decode(info, crc, D, L, llr)
     _say("gpu: " + label)
-    got = gpu_decode(cuda, code, D, L, llr)
+    got = gpu_decode(cuda, code, D, L, llr, lanes=lanes)
     assert_parity(got, ref, label)
     return got, ref, pay
 
@@ -50,33 +53,41 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("N,K,crc,D,L,eb", SMALL)
-def test_gpu_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
+def test_gpu_matches_oracle_f32(cuda, N, K, crc, D, L, eb, lanes):
     B = 37 if N >= 1024 else 101
-    _run(cuda, N, K, crc, D, L, eb, B, seed=11 + N)
+    _run(cuda, N, K, crc, D, L, eb, B, seed=11 + N, lanes=lanes)
 
 
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("N,K,crc,D,L,eb", SMALL[::2])
-def test_gpu_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
+def test_gpu_matches_oracle_i8(cuda, N, K, crc, D, L, eb, lanes):
     B = 37 if N >= 1024 else 101
-    _run(cuda, N, K, crc, D, L, eb, B, seed=23 + N, dtype="i8")
+    _run(cuda, N, K, crc, D, L, eb, B, seed=23 + N, dtype="i8", lanes=lanes)
 
 
-def test_gpu_plain_scs_n64(cuda):
+@pytest.mark.parametrize("lanes", LANES)
+def test_gpu_plain_scs_n64(cuda, lanes):
     """Plain SCS, N=64, K=32, no CRC, D=8, L=8, Eb/N0 2 dB, 10,000 frames."""
-    got, ref, pay = _run(cuda, 64, 32, 0, 8, 8, 2.0, 10000, seed=1, label="plain SCS N=64 10k")
+    got, ref, pay = _run(cuda, 64, 32, 0, 8, 8, 2.0, 10000, seed=1, label="plain SCS N=64 10k",
+                         lanes=lanes)
     assert (got[1] == 1).all()
 
 
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("eb", [1.0, 1.5, 2.0, 2.5, 3.0])
-def test_gpu_n1024_crc16_points(cuda, eb):
+def test_gpu_n1024_crc16_points(cuda, eb, lanes):
     """N=1024, K=512 with CRC-16, D=32, L=8 at each Eb/N0 point of the sweep."""
-    _run(cuda, 1024, 512, 16, 32, 8, eb, 300, seed=2, label="N=1024 sweep %.1f dB" % eb)
+    _run(cuda, 1024, 512, 16, 32, 8, eb, 300, seed=2, label="N=1024 sweep %.1f dB" % eb,
+         lanes=lanes)
 
 
-def test_gpu_fixed_point_n1024(cuda):
+@pytest.mark.parametrize("lanes", LANES)
+def test_gpu_fixed_point_n1024(cuda, lanes):
     """int8 LLRs / int16 path metrics at 2 dB, N=1024, K=512 + CRC-16, D=32."""
-    _run(cuda, 1024, 512, 16, 32, 8, 2.0, 300, seed=2, dtype="i8", label="fixed point N=1024")
+    _run(cuda, 1024, 512, 16, 32, 8, 2.0, 300, seed=2, dtype="i8", label="fixed point N=1024",
+         lanes=lanes)
 
 
 def test_gpu_fixed_point_saturation(cuda):
