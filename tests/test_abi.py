@@ -1,0 +1,108 @@
+"""The C-ABI library on the host: it loads without a GPU, exports every entry point that
+include/polarscs.h declares, and its host-side calls (construction, encoding, argument
+checks) behave as documented.  No decoding runs here."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_03606_amd import binding, channel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polarscs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.library_path()):
+        pytest.fail("libpolarscs.so is not built (run __graft_entry__.build())")
+    return binding.lib()
+
+
+def test_library_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 12, names
+    raw = ctypes.CDLL(binding.library_path())
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(binding.EXPORTS) == set(names)
+
+
+@pytest.mark.parametrize("N,K,crc,db", [(2, 1, 0, 2.0), (8, 4, 0, 2.0), (64, 32, 0, 2.0),
+                                        (128, 32, 16, 2.0), (1024, 512, 16, 2.0),
+                                        (2048, 1707, 16, 2.0), (512, 427, 16, 0.0)])
+def test_construction_and_encoder_match_oracle(lib, N, K, crc, db):
+    code = binding.PolarCode(N, K, crc, db)
+    assert (code.N, code.K, code.crc_bits) == (N, K, crc)
+    assert (code.info_mask == oracle.construct(N, K, db)).all()
+    pay = channel.payload_bits(21, N, 0, 64, K - crc)
+    assert (code.encode(pay) == oracle.encode_batch(code.info_mask, crc, pay)).all()
+
+
+def test_construct_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    for args in [(3, 1, 0), (4096, 8, 0), (1, 1, 0), (64, 0, 0), (64, 65, 0), (64, 32, 8),
+                 (64, 16, 16), (0, 0, 0)]:
+        rc = lib.polar_construct(args[0], args[1], args[2], 2.0, ctypes.byref(h))
+        assert rc == binding.POLAR_EINVAL, args
+    assert lib.polar_construct(64, 32, 0, float("nan"), ctypes.byref(h)) == binding.POLAR_EINVAL
+    assert lib.polar_construct(64, 32, 0, 2.0, None) == binding.POLAR_EINVAL
+
+
+def test_encode_and_decode_reject_bad_arguments(lib):
+    code = binding.PolarCode(64, 32, 0)
+    assert lib.polar_encode(None, None, None, 1) == binding.POLAR_EINVAL
+    assert lib.polar_encode(code.handle, None, None, 1) == binding.POLAR_EINVAL
+    assert lib.polar_encode(code.handle, None, None, 0) == binding.POLAR_OK
+    assert lib.polar_encode(code.handle, None, None, -1) == binding.POLAR_EINVAL
+    # every argument error is caught on the host before any device work
+    assert lib.scs_decode_batch(None, code.handle, 8, 8, 0, None, 1, None, None, None,
+                                None) == binding.POLAR_EINVAL
+    assert lib.scs_ctx_set_lanes(None, 16) == binding.POLAR_EINVAL
+    assert lib.scs_ctx_last_error(None) == binding.POLAR_EINVAL
+    assert lib.polar_code_query(None, None, None, None, None) == binding.POLAR_EINVAL
+    assert lib.polar_strerror(binding.POLAR_EINVAL) == b"invalid argument"
+
+
+def test_query_roundtrip(lib):
+    code = binding.PolarCode(256, 100, 16, 1.5)
+    N, K, r, mask = binding.polar_code_query(code.handle)
+    assert (N, K, r) == (256, 100, 16) and mask.sum() == 100
+
+
+def test_channel_generator_is_seeded_and_chunk_independent():
+    a = channel.noise(5, 7, 0, 70000, 8)
+    b = channel.noise(5, 7, 65530, 100, 8)
+    assert np.array_equal(a[65530:65630], b)
+    p = channel.payload_bits(5, 7, 100, 10, 33)
+    assert np.array_equal(channel.payload_bits(5, 7, 0, 200, 33)[100:110], p)
+    assert not np.array_equal(channel.noise(5, 8, 0, 4, 8), channel.noise(5, 7, 0, 4, 8))
+
+
+def test_channel_llr_formula():
+    cw = np.array([[0, 1, 0, 1]], np.uint8)
+    n = np.array([[0.0, 0.0, 0.5, -0.5]])
+    s2 = channel.sigma2(2.0, 0.5)
+    llr = channel.bpsk_awgn_llr(cw, n, 2.0, 0.5)
+    y = np.array([1.0, -1.0, 1 + 0.5 * np.sqrt(s2), -1 - 0.5 * np.sqrt(s2)])
+    assert np.allclose(llr[0], 2 * y / s2, rtol=1e-6)
+    q = channel.bpsk_awgn_i8(cw, n, 2.0, 0.5, 8.0)
+    assert q.dtype == np.int8 and list(q[0][:2]) == [8, -8]
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
