@@ -48,138 +48,142 @@ namespace {
 template <int LOGN>
 struct Layout {
   static constexpr int N = 1 << LOGN;
-  static constexpr int W = N >= 32 ? N / 32 : 1;     // 32-bit words per bit vector
+  static constexpr int W = N >= 32 ? N / 32 : 1;         // 32-bit words per bit vector
   static constexpr int SMALL = LOGN < 6 ? LOGN - 1 : 5;  // highest stage kept lane-parallel
 };
+
+constexpr uint32_t kLowMask[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
+                                  0x0000FFFFu};
+
+// Partial sums (eq. bitcalc carried through all LAM levels: the polar transform) of the
+// block of 2^LAM decided bits [base, base + 2^LAM) of u, where lane w of u holds bits
+// 32w..32w+31.  This is the beta of the left sibling that g needs (eq. llrcalc); it is
+// computed when needed from the decided bits.  For blocks of <= 32 bits the result is a
+// scalar word whose bit e belongs to position base + e.
+template <int LAM>
+__device__ __forceinline__ uint32_t sibling_small(uint32_t u, int base) {
+  uint32_t x = readlane(u, base >> 5);
+  if constexpr (LAM < 5) x = (x >> (base & 31)) & ((1u << (1 << LAM)) - 1u);
+#pragma unroll
+  for (int s = 0; s < LAM; ++s) x ^= (x >> (1 << s)) & kLowMask[s];
+  return x;
+}
+
+template <int S, int LAM>
+__device__ __forceinline__ void sibling_cross(uint32_t& x, int lane) {
+  if constexpr (S < LAM) {
+    constexpr int dw = 1 << (S - 5);
+    const uint32_t y = xor_lane<dw>(x);
+    if (!(lane & dw)) x ^= y;
+    sibling_cross<S + 1, LAM>(x, lane);
+  }
+}
+
+// Blocks of >= 64 bits: lane-per-word result, zero outside the block.
+template <int LAM>
+__device__ __forceinline__ uint32_t sibling_big(uint32_t u, int base, int lane) {
+  constexpr int NW = (1 << LAM) / 32;
+  const int w0 = base >> 5;
+  uint32_t x = (lane >= w0 && lane < w0 + NW) ? u : 0u;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) x ^= (x >> (1 << s)) & kLowMask[s];
+  sibling_cross<5, LAM>(x, lane);
+  return x;
+}
 
 // Stage LAM >= 6 (Lambda >= 64), then the stages below it down to 6: value e = 64 r + lane
 // of stage lambda from values e and e + Lambda of its parent (eq. llrcalc): f for even
 // phi = i >> lambda, g for odd phi with the partial sums of the left sibling block.
-template <int LAM, int LOGN, class TR>
-__device__ __forceinline__ void big_stages(int top, int i, uint32_t beta,
+template <int LAM, int LOGN, class TR, bool STATS>
+__device__ __forceinline__ void big_stages(int top, int i, uint32_t u,
                                            const typename TR::In* __restrict__ root,
                                            uint32_t* al, int lane, uint32_t& fg) {
   if constexpr (LAM >= 6) {
     if (LAM <= top) {
       constexpr int Lam = 1 << LAM;
       const bool odd = (i >> LAM) & 1;
-      const int bw = ((((i >> LAM) - 1) << LAM) >> 5) + (lane >> 5);
+      const int base = ((i >> LAM) - 1) << LAM;
+      uint32_t bx = 0u;
+      if (odd) bx = sibling_big<LAM>(u, base, lane);
       uint32_t* dst = al + (Lam - 1);
       const uint32_t* src = al + (2 * Lam - 1);
+      if (!odd) {
 #pragma unroll
-      for (int r = 0; r < Lam / kWave; ++r) {
-        const int e = r * kWave + lane;
-        uint32_t pa, pb;
-        if constexpr (LAM + 1 == LOGN) {
-          pa = TR::load(root, e);
-          pb = TR::load(root, e + Lam);
-        } else {
-          pa = src[e];
-          pb = src[e + Lam];
+        for (int r = 0; r < Lam / kWave; ++r) {
+          const int e = r * kWave + lane;
+          if constexpr (LAM + 1 == LOGN)
+            dst[e] = TR::f(TR::load(root, e), TR::load(root, e + Lam));
+          else
+            dst[e] = TR::f(src[e], src[e + Lam]);
         }
-        uint32_t v;
-        if (!odd) {
-          v = TR::f(pa, pb);
-        } else {
-          const uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((bw + 2 * r) << 2, (int)beta);
-          v = TR::g(pa, pb, (w >> (lane & 31)) & 1u);
+      } else {
+#pragma unroll
+        for (int r = 0; r < Lam / kWave; ++r) {
+          const int e = r * kWave + lane;
+          const int w0 = (base >> 5) + 2 * r;
+          const uint32_t mlo = readlane(bx, w0), mhi = readlane(bx, w0 + 1);
+          const uint32_t m = lane < 32 ? mlo : mhi;
+          const bool u = (m >> (lane & 31)) & 1u;
+          if constexpr (LAM + 1 == LOGN)
+            dst[e] = TR::g(TR::load(root, e), TR::load(root, e + Lam), u);
+          else
+            dst[e] = TR::g(src[e], src[e + Lam], u);
         }
-        dst[e] = v;
       }
-      fg += (uint32_t)Lam;
+      if constexpr (STATS) fg += (uint32_t)Lam;
       lds_order();
     }
-    big_stages<LAM - 1, LOGN, TR>(top, i, beta, root, al, lane, fg);
+    big_stages<LAM - 1, LOGN, TR, STATS>(top, i, u, root, al, lane, fg);
   }
 }
 
-template <int LAM, int LOGN, class TR>
-__device__ __forceinline__ void small_chain(uint32_t& x, int start, int i, uint32_t beta,
-                                            uint32_t* al, int lane, uint32_t& fg) {
-  if constexpr (LAM >= 0) {
+// One register stage: value e of stage LAM in lane e from lanes e and e xor Lambda.
+template <int LAM, class TR>
+__device__ __forceinline__ uint32_t reg_stage(uint32_t x, int i, uint32_t u, int lane) {
+  const uint32_t y = xor_lane<(1 << LAM)>(x);
+  if ((i >> LAM) & 1) {
+    const uint32_t m = sibling_small<LAM>(u, ((i >> LAM) - 1) << LAM);
+    return TR::g(x, y, (m >> (lane & 31)) & 1u);
+  }
+  return TR::f(x, y);
+}
+
+template <int LAM, class TR, bool STATS>
+__device__ __forceinline__ void small_chain(uint32_t& x, int start, int i, uint32_t u,
+                                            uint32_t* al, uint32_t* dummy, int lane,
+                                            uint32_t& fg) {
+  if constexpr (LAM >= 1) {
     if (LAM <= start) {
-      const uint32_t y = xor_lane<(1 << LAM)>(x);
-      if (((i >> LAM) & 1) == 0) {
-        x = TR::f(x, y);
-      } else {
-        const int base = ((i >> LAM) - 1) << LAM;
-        const uint32_t m = readlane(beta, base >> 5) >> (base & 31);
-        x = TR::g(x, y, (m >> (lane & 31)) & 1u);
-      }
-      if (lane < (1 << LAM)) al[(1 << LAM) - 1 + lane] = x;
-      fg += 1u << LAM;
+      x = reg_stage<LAM, TR>(x, i, u, lane);
+      // lanes past the stage store into the wave's dummy words instead of masking exec
+      *(lane < (1 << LAM) ? &al[(1 << LAM) - 1 + lane] : &dummy[lane]) = x;
+      if constexpr (STATS) fg += 1u << LAM;
     }
-    small_chain<LAM - 1, LOGN, TR>(x, start, i, beta, al, lane, fg);
+    small_chain<LAM - 1, TR, STATS>(x, start, i, u, al, dummy, lane, fg);
   }
 }
 
-// Stages min(top, SMALL) .. 0 in one register (value e in lane e, partner in lane
-// e xor Lambda); every computed stage is stored for later leaves.  Returns the leaf LLR.
-template <int LOGN, class TR>
-__device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t beta,
+// Stages min(top, SMALL) .. 0 in one register; every computed stage above 0 is stored for
+// later leaves.  Returns the leaf LLR (stage 0 is never a parent and is not stored).
+template <int LOGN, class TR, bool STATS>
+__device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t u,
                                                  const typename TR::In* __restrict__ root,
-                                                 uint32_t* al, int lane, uint32_t& fg) {
+                                                 uint32_t* al, uint32_t* dummy, int lane,
+                                                 uint32_t& fg) {
   constexpr int SM = Layout<LOGN>::SMALL;
   const int start = top < SM ? top : SM;
-  if (start < 0) return (uint32_t)__builtin_amdgcn_readfirstlane((int)al[0]);
-  uint32_t x = 0u;
-  const int nin = 2 << start;  // values of stage start + 1
-  if (start + 1 == LOGN) {
-    if (lane < nin) x = TR::load(root, lane);
-  } else {
-    if (lane < nin) x = al[nin - 1 + lane];
-  }
-  small_chain<SM, LOGN, TR>(x, start, i, beta, al, lane, fg);
+  const int nin = 2 << start;  // values of stage start + 1, read into lanes < nin
+  const int q = lane < nin ? lane : nin - 1;
+  uint32_t x;
+  if (start + 1 == LOGN)
+    x = TR::load(root, q);
+  else
+    x = al[nin - 1 + q];
+  if (start > 0) small_chain<SM, TR, STATS>(x, start, i, u, al, dummy, lane, fg);
+  x = reg_stage<0, TR>(x, i, u, lane);
+  if constexpr (STATS) fg += 1u;
   lds_order();
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-}
-
-// In-place partial sums: write decided bit `bit` at position pos (the path had length pos)
-// and fold every block that this completes (eq. bitcalc: left half ^= right half).
-template <int LOGN>
-__device__ __forceinline__ uint32_t beta_push(uint32_t beta, int pos, uint32_t bit, int lane) {
-  const int w = pos >> 5;
-  uint32_t x = readlane(beta, w);
-  x = (x & ~(1u << (pos & 31))) | (bit << (pos & 31));
-  const int t = __builtin_ctz(~(uint32_t)pos);  // number of completed levels
-  const int tin = t < 5 ? t : 5;
-  for (int lam = 0; lam < tin; ++lam) {
-    const int half = 1 << lam;
-    const int start = ((pos >> (lam + 1)) << (lam + 1)) & 31;
-    x ^= (x >> half) & (((1u << half) - 1u) << start);
-  }
-  beta = (lane == w) ? x : beta;
-  if constexpr (LOGN > 5) {
-    for (int lam = 5; lam < t; ++lam) {
-      const int dw = 1 << (lam - 5);
-      const int a0 = (pos >> (lam + 1)) << (lam + 1 - 5);
-      const uint32_t y = xor_lane_rt(beta, dw);
-      if (lane >= a0 && lane < a0 + dw) beta ^= y;
-    }
-  }
-  return beta;
-}
-
-// In-place partial sums of the first PL bits of u, from scratch: butterfly stage s is
-// applied inside every complete aligned block of 2^(s+1) positions below PL.
-template <int LOGN>
-__device__ __forceinline__ uint32_t beta_build(uint32_t u, int PL, int lane) {
-  uint32_t x = u & prefix_mask(lane, PL);
-  constexpr uint32_t kLow[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
-                                0x0000FFFFu};
-#pragma unroll
-  for (int s = 0; s < (LOGN < 5 ? LOGN : 5); ++s) {
-    const int lim = (PL >> (s + 1)) << (s + 1);
-    x ^= (x >> (1 << s)) & kLow[s] & prefix_mask(lane, lim);
-  }
-#pragma unroll
-  for (int s = 5; s < LOGN; ++s) {
-    const int dw = 1 << (s - 5);
-    const int limw = (PL >> (s + 1)) << (s + 1 - 5);
-    const uint32_t y = xor_lane_rt(x, dw);
-    if (!(lane & dw) && lane < limw) x ^= y;
-  }
-  return x;
 }
 
 struct FrameJob {
@@ -190,15 +194,15 @@ struct FrameJob {
   int D, L;
 };
 
-// LDS words per wave: decided-bit rows, per-length counters, alpha tree.
+// LDS words per wave: decided-bit rows, per-length counters, alpha tree, dummy words.
 inline int lds_words_per_wave(int N, int D) {
   const int W = N >= 32 ? N / 32 : 1;
-  return D * W + (N + 3) / 4 + N;
+  return D * W + (N + 3) / 4 + N + kWave;
 }
 
 // One frame, one wavefront.  `lds` is this wave's private region of
 // lds_words_per_wave(N, D) words.
-template <int LOGN, class TR>
+template <int LOGN, class TR, bool STATS>
 __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJob& job,
                                              uint32_t* lds) {
   using LY = Layout<LOGN>;
@@ -206,11 +210,13 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   constexpr int W = LY::W;
   const int lane = lane_id();
   const int D = job.D, L = job.L;
-  const int crc_bits = code.crc;
+  const bool use_crc = code.crc != 0;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
-  uint32_t* rows = lds;                       // D x W words: decided bits of slot s in row s
-  uint32_t* cnt32 = lds + D * W;              // N bytes: extensions per length
-  uint32_t* al = cnt32 + (N + 3) / 4;         // N - 1 words: alpha stages 0 .. n-1
+  uint32_t* rows = lds;                // D x W words: decided bits of slot s in row s
+  uint32_t* cnt32 = lds + D * W;       // N bytes: extensions per length
+  uint32_t* al = cnt32 + (N + 3) / 4;  // N - 1 words: alpha stages 0 .. n-1
+  uint32_t* dummy = al + N;            // kWave words: stores of lanes that must not store
+  const int wq = lane < W ? lane : W - 1;
 
   const uint32_t infow = lane < W ? code.info[lane] : 0u;
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
@@ -234,9 +240,9 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   int max_slot = 0;
   uint32_t max_hi = 0u, max_lo = 0u;
 
-  // the path held in the tree
+  // the path held in the tree: its length when alpha was last computed, its decided bits
   int wl = -1;
-  uint32_t ucur = 0u, beta = 0u;
+  uint32_t ucur = 0u;
 
   uint32_t fb = 0u, out = 0u;
   bool have_fb = false;
@@ -244,228 +250,215 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   uint32_t st = 0u;
   uint32_t n_it = 0, n_sw = 0, n_cp = 0, n_sc = 0, n_fg = 0, n_ev = 0, n_dr = 0, n_pr = 0;
 
-  const uint32_t cap = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
+  // at most L N extensions and L completions: an unreachable bound that still guarantees
+  // every wavefront leaves the loop
+  uint32_t budget = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
   bool done = false;
-  for (uint32_t guard = 0; !done && guard < cap; ++guard) {
-    if (vmask == 0ull) {
+  while (!done) {
+    if (budget == 0u) {
+      st = 0u;
+      done = true;
+    } else if (vmask == 0ull) {
       st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
       out = fb;
       done = true;
-      break;
-    }
-    // ---- the best path -------------------------------------------------------------
-    int p, pl;
-    uint32_t ppm, plo, pcrc;
-    bool cont;
-    if (have_cand && key_less(cand_hi, cand_lo, lb_hi, lb_lo)) {
-      p = cand_slot;
-      pl = cand_pl;
-      ppm = cand_hi;
-      plo = cand_lo;
-      pcrc = cand_crc;
-      cont = true;
     } else {
-      const bool live = (vmask >> lane) & 1ull;
-      const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
-      const uint32_t mh = wave_min(kh);
-      const uint64_t tie = ballot(kh == mh) & vmask;
-      if (__builtin_popcountll(tie) == 1) {
-        p = __builtin_ctzll(tie);
+      --budget;
+      // ---- the best path -----------------------------------------------------------
+      int p = 0, pl = 0;
+      uint32_t ppm = 0u, plo = 0u, pcrc = 0u;
+      bool cont = false;
+      if (have_cand && key_less(cand_hi, cand_lo, lb_hi, lb_lo)) {
+        p = cand_slot;
+        pl = cand_pl;
+        ppm = cand_hi;
+        plo = cand_lo;
+        pcrc = cand_crc;
+        cont = true;
       } else {
-        const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
-        const uint32_t ml = wave_min(kl);
-        p = __builtin_ctzll(ballot(kl == ml) & tie);
-      }
-      pl = (int)readlane((uint32_t)s_pl, p);
-      plo = readlane(s_lo, p);
-      ppm = mh;
-      pcrc = readlane(s_crc, p);
-      cont = have_cand && p == cand_slot && plo == cand_lo;
-      // lower bound on the keys that stay after p is taken
-      if (__builtin_popcountll(tie) > 1) {
-        lb_hi = mh;
-        lb_lo = 0u;
-      } else {
-        const uint32_t k2 = (live && lane != p) ? s_pm : 0xFFFFFFFFu;
-        lb_hi = wave_min(k2);
-        lb_lo = 0u;
-      }
-    }
-    vmask &= ~(1ull << p);
-    if (have_max && max_slot == p) have_max = false;
-    have_cand = false;
-
-    if (pl == N) {  // a complete path: CRC decides (Section 2.2.5)
-      ++n_cp;
-      const uint32_t row = lane < W ? rows[p * W + lane] : 0u;
-      if (crc_bits == 0 || pcrc == 0u) {
-        st = SCS_STATUS_OK;
-        out = row;
-        done = true;
-      } else {
-        if (!have_fb) {
-          fb = row;
-          have_fb = true;
+        const bool live = (vmask >> lane) & 1ull;
+        const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
+        const uint32_t mh = wave_min(kh);
+        const uint64_t tie = ballot(kh == mh) & vmask;
+        if (__builtin_popcountll(tie) == 1) {
+          p = __builtin_ctzll(tie);
+          const uint32_t k2 = (live && lane != p) ? s_pm : 0xFFFFFFFFu;
+          lb_hi = wave_min(k2);
+        } else {
+          const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
+          const uint32_t ml = wave_min(kl);
+          p = __builtin_ctzll(ballot(kl == ml) & tie);
+          lb_hi = mh;
         }
-        if (++fails >= L) {
-          st = SCS_STATUS_FALLBACK;
-          out = fb;
+        lb_lo = 0u;
+        pl = (int)readlane((uint32_t)s_pl, p);
+        plo = readlane(s_lo, p);
+        ppm = mh;
+        pcrc = readlane(s_crc, p);
+        cont = have_cand && plo == cand_lo;
+      }
+      vmask &= ~(1ull << p);
+      if (have_max && max_slot == p) have_max = false;
+      have_cand = false;
+
+      if (pl == N) {
+        // a complete path: the CRC decides (Section 2.2.5)
+        if constexpr (STATS) ++n_cp;
+        const uint32_t row = lane < W ? rows[p * W + wq] : 0u;
+        if (!use_crc || pcrc == 0u) {
+          st = SCS_STATUS_OK;
+          out = row;
           done = true;
-        }
-      }
-      continue;
-    }
-
-    const int i = pl;
-    ++n_it;
-    n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
-    // L counter of length i (result needed at the end of the iteration)
-    uint32_t old = 0u;
-    if (lane == 0) old = atomicAdd(&cnt32[i >> 2], 1u << (8 * (i & 3)));
-
-    // ---- bring the tree to path p at leaf i ---------------------------------------
-    int top;
-    if (cont) {
-      // the first child of the last extension: the SC schedule continues
-      beta = beta_push<LOGN>(beta, wl, (readlane(ucur, wl >> 5) >> (wl & 31)) & 1u, lane);
-      top = __builtin_ctz((uint32_t)i);
-    } else {
-      ++n_sw;
-      const uint32_t nu = lane < W ? rows[p * W + lane] : 0u;
-      int A, d;
-      if (wl < 0) {
-        A = LOGN;
-        d = 0;
-      } else {
-        const int lim = wl < i ? wl : i;
-        const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
-        const uint64_t bx = ballot(x != 0u);
-        if (bx == 0ull) {
-          d = lim;
         } else {
-          const int w = __builtin_ctzll(bx);
-          d = w * 32 + __builtin_ctz(readlane(x, w));
-        }
-        A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
-      }
-      const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
-      top = (A > Bm ? A : Bm) - 1;
-      if (wl >= 0 && i == wl + 1 && d >= wl)
-        beta = beta_push<LOGN>(beta, wl, (readlane(nu, wl >> 5) >> (wl & 31)) & 1u, lane);
-      else
-        beta = beta_build<LOGN>(nu, i, lane);
-      ucur = nu;
-    }
-    if (top >= 6) big_stages<LOGN - 1, LOGN, TR>(top, i, beta, root, al, lane, n_fg);
-    const uint32_t a0 = small_stages<LOGN, TR>(top, i, beta, root, al, lane, n_fg);
-
-    // ---- leaf decision and children (eq. scest, eq. PMupd) -------------------------
-    const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
-    const bool h = TR::hd(a0);
-    const uint32_t mag = TR::mag(a0);
-    uint32_t b0, pm0, crc0;
-    if (info) {
-      b0 = h ? 1u : 0u;
-      pm0 = ppm;
-      crc0 = crc_step(pcrc, b0);
-    } else {
-      b0 = 0u;
-      pm0 = h ? TR::pm_add(ppm, mag) : ppm;
-      crc0 = pcrc;
-    }
-    const uint32_t seq0 = next_seq++;
-    const uint32_t lo0 = key_lo(N, i + 1, seq0);
-    const int wi = i >> 5;
-    const uint32_t bitm = 1u << (i & 31);
-    if (lane == wi) {
-      ucur = (ucur & ~bitm) | (b0 ? bitm : 0u);
-      rows[p * W + lane] = ucur;
-    }
-    if (lane == p) {
-      s_pm = pm0;
-      s_lo = lo0;
-      s_pl = i + 1;
-      s_crc = crc0;
-    }
-    vmask |= 1ull << p;
-    if (have_max && key_less(max_hi, max_lo, pm0, lo0)) {
-      max_hi = pm0;
-      max_lo = lo0;
-      max_slot = p;
-    }
-
-    if (info) {
-      const uint32_t b1 = b0 ^ 1u;
-      const uint32_t pm1 = TR::pm_add(ppm, mag);
-      const uint32_t crc1 = crc_step(pcrc, b1);
-      const uint32_t seq1 = next_seq++;
-      const uint32_t lo1 = key_lo(N, i + 1, seq1);
-      int t = -1;
-      if (__builtin_popcountll(vmask) < D) {
-        t = __builtin_ctzll(~vmask & dmask);
-        if (have_max && key_less(max_hi, max_lo, pm1, lo1)) {
-          max_hi = pm1;
-          max_lo = lo1;
-          max_slot = t;
-        }
-      } else {
-        if (!have_max) {
-          const bool lv = (vmask >> lane) & 1ull;
-          const uint32_t xh = lv ? s_pm : 0u;
-          const uint32_t Mh = wave_max(xh);
-          const uint64_t tq = ballot(xh == Mh) & vmask;
-          int q;
-          if (__builtin_popcountll(tq) == 1) {
-            q = __builtin_ctzll(tq);
-          } else {
-            const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
-            const uint32_t Ml = wave_max(xl);
-            q = __builtin_ctzll(ballot(xl == Ml) & tq);
+          if (!have_fb) {
+            fb = row;
+            have_fb = true;
           }
-          max_slot = q;
-          max_hi = Mh;
-          max_lo = readlane(s_lo, q);
-          have_max = true;
+          if (++fails >= L) {
+            st = SCS_STATUS_FALLBACK;
+            out = fb;
+            done = true;
+          }
         }
-        if (key_less(pm1, lo1, max_hi, max_lo)) {
-          t = max_slot;
-          have_max = false;
-          ++n_ev;
-        } else {
-          ++n_dr;
+      } else {
+        // ---- extend path p by leaf i -------------------------------------------------
+        const int i = pl;
+        if constexpr (STATS) {
+          ++n_it;
+          n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
         }
-      }
-      if (t >= 0) {
-        if (lane < W) rows[t * W + lane] = ucur ^ (lane == wi ? bitm : 0u);
-        if (lane == t) {
-          s_pm = pm1;
-          s_lo = lo1;
-          s_pl = i + 1;
-          s_crc = crc1;
-        }
-        vmask |= 1ull << t;
-        if (key_less(pm1, lo1, lb_hi, lb_lo)) {
-          lb_hi = pm1;
-          lb_lo = lo1;
-        }
-      }
-    }
-    lds_order();
+        // L counter of length i; lane 0 adds, the others add 0 to their dummy word
+        const uint32_t old = atomicAdd(lane == 0 ? &cnt32[i >> 2] : &dummy[lane],
+                                       lane == 0 ? (1u << (8 * (i & 3))) : 0u);
 
-    // L-counter pruning
-    old = readlane(old, 0);
-    if ((int)((old >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
-      ++n_pr;
-      vmask &= ~ballot(s_pl <= i);
-      have_max = false;
+        int top = 0;
+        if (cont) {
+          top = __builtin_ctz((uint32_t)i);  // the SC schedule continues (i = wl + 1 > 0)
+        } else {
+          if constexpr (STATS) ++n_sw;
+          const uint32_t nu = lane < W ? rows[p * W + wq] : 0u;
+          int A = LOGN, d = 0;
+          if (wl < 0) {
+            A = LOGN;
+            d = 0;
+          } else {
+            const int lim = wl < i ? wl : i;
+            const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
+            const uint64_t bx = ballot(x != 0u);
+            if (bx == 0ull) {
+              d = lim;
+            } else {
+              const int w = __builtin_ctzll(bx);
+              d = w * 32 + __builtin_ctz(readlane(x, w));
+            }
+            A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
+          }
+          const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
+          top = (A > Bm ? A : Bm) - 1;
+          if (top < 0) top = 0;
+          ucur = nu;
+        }
+        if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
+        const uint32_t a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+
+        // ---- leaf decision and children (eq. scest, eq. PMupd) -----------------------
+        const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
+        const bool h = TR::hd(a0);
+        const uint32_t pm1 = TR::pm_add(ppm, TR::mag(a0));  // metric against the decision
+        const uint32_t b0 = (info && h) ? 1u : 0u;
+        const uint32_t pm0 = (!info && h) ? pm1 : ppm;
+        const uint32_t crc0 = info ? crc_step(pcrc, b0) : pcrc;
+        const uint32_t seq0 = next_seq;
+        next_seq += info ? 2u : 1u;
+        const uint32_t lo0 = key_lo(N, i + 1, seq0);
+        const int wi = i >> 5;
+        const uint32_t bitm = 1u << (i & 31);
+        ucur = (lane == wi) ? ((ucur & ~bitm) | (b0 ? bitm : 0u)) : ucur;
+        *(lane == wi ? &rows[p * W + wi] : &dummy[lane]) = ucur;
+        if (lane == p) {
+          s_pm = pm0;
+          s_lo = lo0;
+          s_pl = i + 1;
+          s_crc = crc0;
+        }
+        vmask |= 1ull << p;
+        if (have_max && key_less(max_hi, max_lo, pm0, lo0)) {
+          max_hi = pm0;
+          max_lo = lo0;
+          max_slot = p;
+        }
+
+        if (info) {
+          // the flipped child: its CRC register differs by the polynomial (feedback flips)
+          const uint32_t crc1 = crc0 ^ 0x1021u;
+          const uint32_t lo1 = lo0 + 1u;  // next sequence number, same length
+          int t = -1;
+          if (__builtin_popcountll(vmask) < D) {
+            t = __builtin_ctzll(~vmask & dmask);
+            if (have_max && key_less(max_hi, max_lo, pm1, lo1)) {
+              max_hi = pm1;
+              max_lo = lo1;
+              max_slot = t;
+            }
+          } else {
+            if (!have_max) {
+              const bool lv = (vmask >> lane) & 1ull;
+              const uint32_t xh = lv ? s_pm : 0u;
+              const uint32_t Mh = wave_max(xh);
+              const uint64_t tq = ballot(xh == Mh) & vmask;
+              int q;
+              if (__builtin_popcountll(tq) == 1) {
+                q = __builtin_ctzll(tq);
+              } else {
+                const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
+                const uint32_t Ml = wave_max(xl);
+                q = __builtin_ctzll(ballot(xl == Ml) & tq);
+              }
+              max_slot = q;
+              max_hi = Mh;
+              max_lo = readlane(s_lo, q);
+              have_max = true;
+            }
+            if (key_less(pm1, lo1, max_hi, max_lo)) {
+              t = max_slot;
+              have_max = false;
+              if constexpr (STATS) ++n_ev;
+            } else {
+              if constexpr (STATS) ++n_dr;
+            }
+          }
+          if (t >= 0) {
+            *(lane < W ? &rows[t * W + wq] : &dummy[lane]) = ucur ^ (lane == wi ? bitm : 0u);
+            if (lane == t) {
+              s_pm = pm1;
+              s_lo = lo1;
+              s_pl = i + 1;
+              s_crc = crc1;
+            }
+            vmask |= 1ull << t;
+            if (key_less(pm1, lo1, lb_hi, lb_lo)) {
+              lb_hi = pm1;
+              lb_lo = lo1;
+            }
+          }
+        }
+        lds_order();
+
+        // L-counter pruning
+        if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
+          if constexpr (STATS) ++n_pr;
+          vmask &= ~ballot(s_pl <= i);
+          have_max = false;
+        }
+        wl = i;
+        have_cand = true;
+        cand_slot = p;
+        cand_pl = i + 1;
+        cand_hi = pm0;
+        cand_lo = lo0;
+        cand_crc = crc0;
+      }
     }
-    wl = i;
-    have_cand = true;
-    cand_slot = p;
-    cand_pl = i + 1;
-    cand_hi = pm0;
-    cand_lo = lo0;
-    cand_crc = crc0;
   }
 
   // output: payload = the first K - r information bits of the output path
@@ -481,7 +474,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     }
   }
   if (lane == 0) *job.status = (uint8_t)st;
-  if (job.stats) {
+  if constexpr (STATS) {
     const uint32_t v[8] = {n_it, n_sw, n_cp, n_sc, n_fg, n_ev, n_dr, n_pr};
     if (lane < 8) {
       uint32_t x = v[0];
@@ -492,7 +485,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   }
 }
 
-template <int LOGN, class TR>
+template <int LOGN, class TR, bool STATS>
 __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, int L,
                                                           const typename TR::In* __restrict__ llr,
                                                           int64_t n_frames,
@@ -509,10 +502,10 @@ __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, 
   job.llr = llr + frame * N;
   job.payload = payload + frame * code.kp;
   job.status = status + frame;
-  job.stats = stats ? stats + frame : nullptr;
+  job.stats = STATS ? stats + frame : nullptr;
   job.D = D;
   job.L = L;
-  decode_frame<LOGN, TR>(code, job, lds + wave * wave_words);
+  decode_frame<LOGN, TR, STATS>(code, job, lds + wave * wave_words);
 }
 
 // ------------------------------------------------------------------------------------
@@ -567,22 +560,27 @@ template <class TR>
 using UniformKernel = void (*)(CodeArgs, int, int, const typename TR::In*, int64_t, uint8_t*,
                                uint8_t*, scs_stats*, int);
 
-template <class TR>
-UniformKernel<TR> uniform_kernel_for(int logn) {
+template <class TR, bool STATS>
+UniformKernel<TR> uniform_kernel_for_t(int logn) {
   switch (logn) {
-    case 1: return scs_uniform_kernel<1, TR>;
-    case 2: return scs_uniform_kernel<2, TR>;
-    case 3: return scs_uniform_kernel<3, TR>;
-    case 4: return scs_uniform_kernel<4, TR>;
-    case 5: return scs_uniform_kernel<5, TR>;
-    case 6: return scs_uniform_kernel<6, TR>;
-    case 7: return scs_uniform_kernel<7, TR>;
-    case 8: return scs_uniform_kernel<8, TR>;
-    case 9: return scs_uniform_kernel<9, TR>;
-    case 10: return scs_uniform_kernel<10, TR>;
-    case 11: return scs_uniform_kernel<11, TR>;
+    case 1: return scs_uniform_kernel<1, TR, STATS>;
+    case 2: return scs_uniform_kernel<2, TR, STATS>;
+    case 3: return scs_uniform_kernel<3, TR, STATS>;
+    case 4: return scs_uniform_kernel<4, TR, STATS>;
+    case 5: return scs_uniform_kernel<5, TR, STATS>;
+    case 6: return scs_uniform_kernel<6, TR, STATS>;
+    case 7: return scs_uniform_kernel<7, TR, STATS>;
+    case 8: return scs_uniform_kernel<8, TR, STATS>;
+    case 9: return scs_uniform_kernel<9, TR, STATS>;
+    case 10: return scs_uniform_kernel<10, TR, STATS>;
+    case 11: return scs_uniform_kernel<11, TR, STATS>;
   }
   return nullptr;
+}
+
+template <class TR>
+UniformKernel<TR> uniform_kernel_for(int logn, bool stats) {
+  return stats ? uniform_kernel_for_t<TR, true>(logn) : uniform_kernel_for_t<TR, false>(logn);
 }
 
 int waves_per_block(int N, int D) {
@@ -703,12 +701,12 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   const int64_t blocks = (n_frames + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
   if (llr_dtype == SCS_LLR_F32) {
-    auto k = uniform_kernel_for<TrF32>(code->logn);
+    auto k = uniform_kernel_for<TrF32>(code->logn, stats_dev != nullptr);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
                        (const float*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
                        wave_words);
   } else {
-    auto k = uniform_kernel_for<TrI8>(code->logn);
+    auto k = uniform_kernel_for<TrI8>(code->logn, stats_dev != nullptr);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
                        (const int8_t*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
                        wave_words);
