@@ -85,9 +85,10 @@ int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
 
 typedef struct scs_ctx scs_ctx; /* per-device decoder context */
 
-/* Create a context on HIP device `device`.  It owns the device-side code tables used by
- * mixed batches and a small work counter; it allocates nothing once created except when
- * a mixed batch needs more table space than any earlier one. */
+/* Create a context on HIP device `device`.  It owns the device-side code tables and frame
+ * descriptors of mixed batches, their work counter and a pinned staging buffer; after
+ * creation it allocates only when a mixed batch needs more table space than any earlier
+ * one.  Errors: POLAR_EINVAL for a bad device, POLAR_EDEVICE if HIP fails. */
 int scs_ctx_create(int device, scs_ctx** out);
 void scs_ctx_destroy(scs_ctx* ctx);
 
@@ -147,15 +148,28 @@ typedef struct {
 } scs_frame;
 
 /* Decode frames of different codes, depths and list sizes in one persistent launch.
- * frames_host: n_frames descriptors in host memory (validated on the host, then copied
- * into the context's device buffer on hip_stream).  Frame f writes status_dev[f] and,
- * if stats_dev is not NULL, stats_dev[f].  The result of every frame equals what
- * scs_decode_batch gives for it alone.  Errors: POLAR_EINVAL for a bad code index, D, L,
- * _pad, or an offset that is negative. */
+ * frames_host: n_frames descriptors in host memory, validated on the host and copied with
+ * the code tables into the context's device buffers on hip_stream.  Frame f writes
+ * status_dev[f] and, if stats_dev is not NULL, stats_dev[f]; its payload goes to
+ * payload_dev + out_off.  The result of every frame equals what scs_decode_batch gives for
+ * it alone.  Equivalent to scs_mixed_prepare followed by scs_mixed_launch.  Errors:
+ * POLAR_EINVAL for a bad code index, D, L, _pad, a negative offset or a NULL buffer;
+ * POLAR_EUNSUPPORTED when one frame's decoder state would not fit 64 KB of LDS. */
 int scs_decode_mixed(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
                      const scs_frame* frames_host, int64_t n_frames, int32_t llr_dtype,
                      const void* llr_dev, uint8_t* payload_dev, uint8_t* status_dev,
                      scs_stats* stats_dev, void* hip_stream);
+
+/* The two halves of scs_decode_mixed.  prepare validates and uploads a batch plan (it may
+ * allocate, growing the context's buffers, and waits for the previous upload to finish);
+ * launch enqueues the decoding of the prepared plan and neither allocates, copies nor
+ * sets memory from the host, so a caller can capture it in a HIP graph and replay it while
+ * the plan and the buffers stay the same.  The codes passed to prepare must outlive the
+ * last launch of that plan. */
+int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                      const scs_frame* frames_host, int64_t n_frames, void* hip_stream);
+int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8_t* payload_dev,
+                     uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream);
 
 /* Last HIP error seen by a call on this context (POLAR_OK if none), then cleared. */
 int scs_ctx_last_error(scs_ctx* ctx);

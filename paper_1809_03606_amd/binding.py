@@ -24,7 +24,8 @@ SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
-           "scs_decode_mixed", "scs_ctx_set_lanes", "scs_ctx_last_error", "polar_strerror")
+           "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
+           "scs_ctx_last_error", "polar_strerror")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
                 "drops", "prunes")
@@ -74,13 +75,16 @@ def lib():
             L.scs_ctx_destroy.restype = None
             L.scs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
             L.scs_decode_mixed.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
+            L.scs_mixed_prepare.argtypes = [vp, vp, i32, vp, i64, vp]
+            L.scs_mixed_launch.argtypes = [vp, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
             L.scs_ctx_set_lanes.argtypes = [vp, i32]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
-                      "scs_ctx_set_lanes", "scs_ctx_last_error"):
+                      "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
+                      "scs_ctx_last_error"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -170,12 +174,27 @@ def scs_decode_batch(ctx: int, code: int, D: int, L: int, llr_dtype: int, llr_de
 
 def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_dev, payload_dev,
                      status_dev, stats_dev=None, stream=None):
-    arr = (ctypes.c_void_p * len(codes))(*codes)
+    arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
     fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
     _check(lib().scs_decode_mixed(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
                                   fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
                                   _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
                                   _addr(stats_dev), _stream(stream)), "scs_decode_mixed")
+
+
+def scs_mixed_prepare(ctx: int, codes, frames: np.ndarray, stream=None):
+    arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
+    fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    _check(lib().scs_mixed_prepare(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
+                                   fr.ctypes.data, int(fr.shape[0]), _stream(stream)),
+           "scs_mixed_prepare")
+
+
+def scs_mixed_launch(ctx: int, llr_dtype: int, llr_dev, payload_dev, status_dev, stats_dev=None,
+                     stream=None):
+    _check(lib().scs_mixed_launch(ctx, int(llr_dtype), _addr(llr_dev), _addr(payload_dev),
+                                  _addr(status_dev), _addr(stats_dev), _stream(stream)),
+           "scs_mixed_launch")
 
 
 def scs_ctx_set_lanes(ctx: int, lanes_per_frame: int):

@@ -101,3 +101,24 @@ def device_llr(torch, gen, codeword, ebn0_db: float, rate: float, dtype: str = "
     if dtype == "f32":
         return ((2.0 * y) / s2).to(torch.float32)
     return torch.clamp(torch.round(scale * y), -127, 127).to(torch.int8)
+
+
+# -- mixed batches -------------------------------------------------------------------
+
+MIXED_N = (128, 256, 512, 1024, 2048)
+MIXED_RATES = ((1, 4), (1, 3), (1, 2), (2, 3), (5, 6))
+MIXED_D = (8, 32, 64)
+
+
+def mixed_codes():
+    """The 25 (N, K) pairs of the mixed workload, K = floor(N p / q + 1/2) (CRC inside K)."""
+    return [(n, (n * p + q // 2) // q) for n in MIXED_N for (p, q) in MIXED_RATES]
+
+
+def mixed_draw(seed: int, B: int):
+    """Per-frame code index (into mixed_codes()), stack depth and Eb/N0 ~ U[1.5, 3.5]."""
+    g = np.random.Generator(np.random.Philox(key=[int(seed), 0x6D6978]))
+    code = g.integers(0, len(MIXED_N) * len(MIXED_RATES), size=B)
+    D = np.asarray(MIXED_D)[g.integers(0, len(MIXED_D), size=B)]
+    ebn0 = g.uniform(1.5, 3.5, size=B)
+    return code.astype(np.int32), D.astype(np.int32), ebn0

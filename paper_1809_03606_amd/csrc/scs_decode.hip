@@ -509,6 +509,68 @@ __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, 
 }
 
 // ------------------------------------------------------------------------------------
+// Mixed batches: one persistent launch, frames of any code / D / L taken from an atomic
+// work counter in the order given by `order` (largest frames first), one frame per wave.
+// ------------------------------------------------------------------------------------
+template <class TR, bool STATS>
+__device__ __forceinline__ void decode_any(int logn, const CodeArgs& code, const FrameJob& job,
+                                           uint32_t* lds) {
+  switch (logn) {
+    case 1: decode_frame<1, TR, STATS>(code, job, lds); break;
+    case 2: decode_frame<2, TR, STATS>(code, job, lds); break;
+    case 3: decode_frame<3, TR, STATS>(code, job, lds); break;
+    case 4: decode_frame<4, TR, STATS>(code, job, lds); break;
+    case 5: decode_frame<5, TR, STATS>(code, job, lds); break;
+    case 6: decode_frame<6, TR, STATS>(code, job, lds); break;
+    case 7: decode_frame<7, TR, STATS>(code, job, lds); break;
+    case 8: decode_frame<8, TR, STATS>(code, job, lds); break;
+    case 9: decode_frame<9, TR, STATS>(code, job, lds); break;
+    case 10: decode_frame<10, TR, STATS>(code, job, lds); break;
+    case 11: decode_frame<11, TR, STATS>(code, job, lds); break;
+    default: break;
+  }
+}
+
+// Zeroes the work counter on the launch stream (a kernel, so that the launch can be
+// captured in a graph without memset nodes).
+__global__ void reset_counter_kernel(uint32_t* counter) { *counter = 0u; }
+
+template <class TR, bool STATS>
+__global__ __launch_bounds__(256) void scs_mixed_kernel(const CodeArgs* __restrict__ codes,
+                                                        const scs_frame* __restrict__ frames,
+                                                        const int32_t* __restrict__ order,
+                                                        uint32_t n_frames,
+                                                        const typename TR::In* __restrict__ llr,
+                                                        uint8_t* __restrict__ payload,
+                                                        uint8_t* __restrict__ status,
+                                                        scs_stats* __restrict__ stats,
+                                                        uint32_t* __restrict__ counter,
+                                                        int wave_words) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  uint32_t* mine = lds + wave * wave_words;
+  for (;;) {
+    uint32_t k = 0u;
+    if (lane == 0) k = atomicAdd(counter, 1u);
+    k = readlane(k, 0);
+    if (k >= n_frames) break;  // every wave leaves once the queue is empty
+    const int f = order[k];
+    const scs_frame d = frames[f];
+    const CodeArgs& code = codes[d.code];
+    FrameJob job;
+    job.llr = llr + d.llr_off;
+    job.payload = payload + d.out_off;
+    job.status = status + f;
+    job.stats = STATS ? stats + f : nullptr;
+    job.D = d.D;
+    job.L = d.L;
+    decode_any<TR, STATS>(code.logn, code, job, mine);
+    lds_order();
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // Device encoder: one wave per frame, lane w owns bits 32w..32w+31 of u.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void encode_kernel(CodeArgs code, const uint16_t* __restrict__ crc_unit,
@@ -596,7 +658,21 @@ struct scs_ctx {
   int device = 0;
   int lanes = 0;  // lanes per frame: 0 = automatic, else 16, 32 or 64
   int last_error = POLAR_OK;
+  int cus = 0;    // compute units of the device
   std::mutex mu;
+  // mixed-batch plan: device copies of the code tables, descriptors and the frame order,
+  // the work counter, and a pinned staging area for the uploads
+  CodeArgs* d_codes = nullptr;
+  size_t cap_codes = 0;
+  scs_frame* d_frames = nullptr;
+  int32_t* d_order = nullptr;
+  size_t cap_frames = 0;
+  uint32_t* d_counter = nullptr;
+  char* h_stage = nullptr;
+  size_t cap_stage = 0;
+  hipEvent_t staged = nullptr;
+  uint32_t plan_frames = 0;
+  int plan_wave_words = 0;
 };
 
 namespace {
@@ -630,11 +706,34 @@ int scs_ctx_create(int device, scs_ctx** out) {
   scs_ctx* c = new (std::nothrow) scs_ctx;
   if (!c) return POLAR_ENOMEM;
   c->device = device;
+  int dev0 = 0;
+  hipGetDevice(&dev0);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipMalloc(&c->d_counter, sizeof(uint32_t)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
+    hipFree(c->d_counter);
+    delete c;
+    hipSetDevice(dev0);
+    return POLAR_EDEVICE;
+  }
+  hipSetDevice(dev0);
   *out = c;
   return POLAR_OK;
 }
 
-void scs_ctx_destroy(scs_ctx* ctx) { delete ctx; }
+void scs_ctx_destroy(scs_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  hipFree(ctx->d_codes);
+  hipFree(ctx->d_frames);
+  hipFree(ctx->d_order);
+  hipFree(ctx->d_counter);
+  if (ctx->h_stage) hipHostFree(ctx->h_stage);
+  if (ctx->staged) hipEventDestroy(ctx->staged);
+  delete ctx;
+}
 
 int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame) {
   if (!ctx) return POLAR_EINVAL;
@@ -720,9 +819,133 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   return POLAR_OK;
 }
 
-int scs_decode_mixed(scs_ctx*, const polar_code* const*, int32_t, const scs_frame*, int64_t,
-                     int32_t, const void*, uint8_t*, uint8_t*, scs_stats*, void*) {
-  return POLAR_EUNSUPPORTED;
+int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                      const scs_frame* frames_host, int64_t n_frames, void* hip_stream) {
+  if (!ctx || n_frames < 0 || n_codes < 0 || n_frames > 0x7FFFFFFF) return POLAR_EINVAL;
+  if (n_frames > 0 && (!codes || n_codes < 1 || !frames_host)) return POLAR_EINVAL;
+  for (int32_t c = 0; c < n_codes; ++c)
+    if (!codes[c] || codes[c]->logn < 1 || codes[c]->logn > 11) return POLAR_EINVAL;
+  int wave_words = 0;
+  for (int64_t f = 0; f < n_frames; ++f) {
+    const scs_frame& d = frames_host[f];
+    if (d.code < 0 || d.code >= n_codes || d.D < 1 || d.D > 64 || d.L < 1 || d.L > 255 ||
+        d._pad != 0 || d.llr_off < 0 || d.out_off < 0)
+      return POLAR_EINVAL;
+    wave_words = std::max(wave_words, lds_words_per_wave(codes[d.code]->N, d.D));
+  }
+  if ((size_t)wave_words * 4 > 64 * 1024) return POLAR_EUNSUPPORTED;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // largest frames first, so that the work queue ends with short frames
+  std::vector<int32_t> order((size_t)n_frames);
+  for (int64_t f = 0; f < n_frames; ++f) order[f] = (int32_t)f;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const int64_t wa = (int64_t)codes[frames_host[a].code]->N * frames_host[a].L;
+    const int64_t wb = (int64_t)codes[frames_host[b].code]->N * frames_host[b].L;
+    return wa > wb;
+  });
+  const size_t nc = (size_t)std::max(n_codes, 1), nf = (size_t)std::max<int64_t>(n_frames, 1);
+  // grow-only device buffers (earlier launches may still read the old ones)
+  if (nc > ctx->cap_codes || nf > ctx->cap_frames) {
+    if (hipDeviceSynchronize() != hipSuccess) return POLAR_EDEVICE;
+    if (nc > ctx->cap_codes) {
+      hipFree(ctx->d_codes);
+      ctx->d_codes = nullptr;
+      if (hipMalloc(&ctx->d_codes, nc * sizeof(CodeArgs)) != hipSuccess) return POLAR_ENOMEM;
+      ctx->cap_codes = nc;
+    }
+    if (nf > ctx->cap_frames) {
+      hipFree(ctx->d_frames);
+      hipFree(ctx->d_order);
+      ctx->d_frames = nullptr;
+      ctx->d_order = nullptr;
+      if (hipMalloc(&ctx->d_frames, nf * sizeof(scs_frame)) != hipSuccess ||
+          hipMalloc(&ctx->d_order, nf * sizeof(int32_t)) != hipSuccess)
+        return POLAR_ENOMEM;
+      ctx->cap_frames = nf;
+    }
+  }
+  const size_t bytes = nc * sizeof(CodeArgs) + nf * sizeof(scs_frame) + nf * sizeof(int32_t);
+  if (hipEventSynchronize(ctx->staged) != hipSuccess) return POLAR_EDEVICE;  // staging free
+  if (bytes > ctx->cap_stage) {
+    if (ctx->h_stage) hipHostFree(ctx->h_stage);
+    ctx->h_stage = nullptr;
+    if (hipHostMalloc((void**)&ctx->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
+      return POLAR_ENOMEM;
+    ctx->cap_stage = bytes;
+  }
+  CodeArgs* hc = (CodeArgs*)ctx->h_stage;
+  scs_frame* hf = (scs_frame*)(ctx->h_stage + nc * sizeof(CodeArgs));
+  int32_t* ho = (int32_t*)(ctx->h_stage + nc * sizeof(CodeArgs) + nf * sizeof(scs_frame));
+  for (int32_t c = 0; c < n_codes; ++c) hc[c] = make_args(codes[c]);
+  if (n_frames) {
+    std::memcpy(hf, frames_host, (size_t)n_frames * sizeof(scs_frame));
+    std::memcpy(ho, order.data(), (size_t)n_frames * sizeof(int32_t));
+  }
+  if (hipMemcpyAsync(ctx->d_codes, hc, nc * sizeof(CodeArgs), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ctx->d_frames, hf, nf * sizeof(scs_frame), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ctx->d_order, ho, nf * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(ctx->staged, s) != hipSuccess)
+    return POLAR_EDEVICE;
+  ctx->plan_frames = (uint32_t)n_frames;
+  ctx->plan_wave_words = wave_words;
+  return POLAR_OK;
+}
+
+int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8_t* payload_dev,
+                     uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream) {
+  if (!ctx) return POLAR_EINVAL;
+  if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
+  if (ctx->plan_frames == 0) return POLAR_OK;
+  if (!llr_dev || !status_dev || !payload_dev) return POLAR_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int ww = ctx->plan_wave_words;
+  int wpb = 4;
+  while (wpb > 1 && (size_t)wpb * ww * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * ww * 4;
+  const bool st = stats_dev != nullptr;
+  const void* kfun;
+  if (llr_dtype == SCS_LLR_F32)
+    kfun = st ? (const void*)scs_mixed_kernel<TrF32, true> : (const void*)scs_mixed_kernel<TrF32, false>;
+  else
+    kfun = st ? (const void*)scs_mixed_kernel<TrI8, true> : (const void*)scs_mixed_kernel<TrI8, false>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun, 64 * wpb, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int64_t need = ((int64_t)ctx->plan_frames + wpb - 1) / wpb;
+  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, need);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, ctx->d_counter);
+  if (llr_dtype == SCS_LLR_F32) {
+    auto k = st ? scs_mixed_kernel<TrF32, true> : scs_mixed_kernel<TrF32, false>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, ctx->d_codes, ctx->d_frames,
+                       ctx->d_order, ctx->plan_frames, (const float*)llr_dev, payload_dev,
+                       status_dev, stats_dev, ctx->d_counter, ww);
+  } else {
+    auto k = st ? scs_mixed_kernel<TrI8, true> : scs_mixed_kernel<TrI8, false>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, ctx->d_codes, ctx->d_frames,
+                       ctx->d_order, ctx->plan_frames, (const int8_t*)llr_dev, payload_dev,
+                       status_dev, stats_dev, ctx->d_counter, ww);
+  }
+  if (hipGetLastError() != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->last_error = POLAR_EDEVICE;
+    return POLAR_EDEVICE;
+  }
+  return POLAR_OK;
+}
+
+int scs_decode_mixed(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                     const scs_frame* frames_host, int64_t n_frames, int32_t llr_dtype,
+                     const void* llr_dev, uint8_t* payload_dev, uint8_t* status_dev,
+                     scs_stats* stats_dev, void* hip_stream) {
+  if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
+  if (n_frames > 0 && (!llr_dev || !status_dev || !payload_dev)) return POLAR_EINVAL;
+  const int rc = scs_mixed_prepare(ctx, codes, n_codes, frames_host, n_frames, hip_stream);
+  if (rc != POLAR_OK) return rc;
+  return scs_mixed_launch(ctx, llr_dtype, llr_dev, payload_dev, status_dev, stats_dev, hip_stream);
 }
 
 int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
