@@ -57,6 +57,13 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
                     help="lanes per frame (0: the library's choice)")
+    ap.add_argument("--workload", choices=("sweep", "mixed", "serve"), default="sweep",
+                    help="sweep: PC(1024,512) headline; mixed: 25 codes / 3 depths in one launch; "
+                         "serve: Poisson requests through the continuous-batching server")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load as a fraction of the measured saturated capacity")
+    ap.add_argument("--mixed-frames", type=int, default=2_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -105,6 +112,12 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.workload in ("mixed", "serve"):
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        (run_mixed if args.workload == "mixed" else run_serve)(args)
         return
     if args.gpus != 1:
         print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
@@ -272,6 +285,211 @@ def main():
         "wall_s": wall, "input_generation_s": gen_s,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def run_mixed(args):
+    """Mixed batch: frames drawn uniformly over N in {128..2048}, rate in {1/4..5/6} (25
+    codes, CRC-16), D in {8, 32, 64}, L = 8, Eb/N0 ~ U[1.5, 3.5] dB, decoded (a) in one
+    persistent launch replayed from a captured graph and (b) as one launch per (code, D)."""
+    import torch
+
+    from paper_1809_03606_amd import binding, channel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    B, Lp, crc, seed = args.mixed_frames, 8, 16, 4
+    codes = channel.mixed_codes()
+    pcs = [binding.PolarCode(n, k, crc, 2.0) for (n, k) in codes]
+    cidx, Dv, eb = channel.mixed_draw(seed, B)
+    dsel = {8: 0, 32: 1, 64: 2}
+    gkey = cidx.astype(np.int64) * 3 + np.vectorize(dsel.get)(Dv)
+    grouped = np.argsort(gkey, kind="stable")  # frames grouped by (code, D)
+    Nf = np.array([codes[c][0] for c in cidx], np.int64)
+    kpf = np.array([codes[c][1] - crc for c in cidx], np.int64)
+    llr_off = np.zeros(B, np.int64)
+    out_off = np.zeros(B, np.int64)
+    llr_off[grouped] = np.concatenate([[0], np.cumsum(Nf[grouped])[:-1]])
+    out_off[grouped] = np.concatenate([[0], np.cumsum(kpf[grouped])[:-1]])
+    tot_llr, tot_out = int(Nf.sum()), int(kpf.sum())
+    stream = torch.cuda.Stream(device=dev)
+    llr = torch.empty(tot_llr, dtype=torch.float32, device=dev)
+    pay_ref = torch.empty(tot_out, dtype=torch.uint8, device=dev)
+    groups = []  # (code, D, first grouped position, count)
+    t0 = time.time()
+    with torch.cuda.stream(stream):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        bounds = np.nonzero(np.diff(gkey[grouped]))[0] + 1
+        for a, b in zip(np.concatenate([[0], bounds]), np.concatenate([bounds, [B]])):
+            f0 = grouped[a]
+            c, d = int(cidx[f0]), int(Dv[f0])
+            n, k = codes[c]
+            lo, lo_o = int(llr_off[f0]), int(out_off[f0])
+            cnt = int(b - a)
+            pay = channel.device_payload(torch, gen, cnt, k - crc, dev)
+            cw = torch.empty((cnt, n), dtype=torch.uint8, device=dev)
+            pcs[c].encode_device(pay, cw, stream)
+            ebs = torch.from_numpy(eb[grouped[a:b]]).to(dev)
+            llr[lo:lo + cnt * n] = channel.device_llr_per_frame(torch, gen, cw, ebs, k / n).reshape(-1)
+            pay_ref[lo_o:lo_o + cnt * (k - crc)] = pay.reshape(-1)
+            groups.append((c, d, lo, lo_o, cnt))
+    stream.synchronize()
+    log("mixed inputs ready: %d frames in %d (code, D) groups, %.1f s" % (B, len(groups), time.time() - t0))
+
+    frames = np.zeros(B, binding.FRAME_DTYPE)
+    frames["code"], frames["D"], frames["L"] = cidx, Dv, Lp
+    frames["llr_off"], frames["out_off"] = llr_off, out_off
+    ctx = binding.ScsContext(0)
+    pay_m = torch.empty(tot_out, dtype=torch.uint8, device=dev)
+    st_m = torch.empty(B, dtype=torch.uint8, device=dev)
+    pay_p = torch.empty(tot_out, dtype=torch.uint8, device=dev)
+    st_p = torch.empty(B, dtype=torch.uint8, device=dev)
+    handles = [p.handle for p in pcs]
+    binding.scs_mixed_prepare(ctx.handle, handles, frames, stream)
+    stream.synchronize()
+
+    def plain():
+        pos = 0
+        for (c, d, lo, lo_o, cnt) in groups:
+            n, k = codes[c]
+            binding.scs_decode_batch(ctx.handle, pcs[c].handle, d, Lp, binding.SCS_LLR_F32,
+                                     llr[lo:].data_ptr(), cnt, pay_p[lo_o:].data_ptr(),
+                                     st_p[pos:].data_ptr(), None, stream)
+            pos += cnt
+
+    # graph of the prepared persistent launch
+    g = torch.cuda.CUDAGraph()
+    binding.scs_mixed_launch(ctx.handle, binding.SCS_LLR_F32, llr, pay_m, st_m, None, stream)
+    stream.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        binding.scs_mixed_launch(ctx.handle, binding.SCS_LLR_F32, llr, pay_m, st_m, None,
+                                 torch.cuda.current_stream())
+    plain()
+    stream.synchronize()
+    same = bool(torch.equal(pay_m, pay_p)) and bool(torch.equal(st_m[torch.from_numpy(grouped).to(dev)], st_p))
+    # frame errors: compare per frame via segment sums over the payload bytes
+    bad = (pay_m != pay_ref).to(torch.int64)
+    seg = torch.from_numpy(np.repeat(np.arange(B)[grouped], kpf[grouped])).to(dev)
+    err_frames = torch.zeros(B, dtype=torch.int64, device=dev).index_add_(0, seg, bad)
+    fer = float((err_frames > 0).float().mean().item())
+    log("mixed: outputs equal to the per-configuration launches: %s, FER %.3e" % (same, fer))
+
+    def timed(fn, reps):
+        ev = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            ev.append((a, b))
+        stream.synchronize()
+        return [a.elapsed_time(b) for a, b in ev]
+
+    with torch.cuda.stream(stream):
+        timed(g.replay, args.warmup)
+        ms_m = timed(g.replay, args.steps)
+    timed(plain, args.warmup)
+    ms_p = timed(plain, args.steps)
+    bits = B * float(kpf.mean())
+    v_m = bits / (np.mean(ms_m) * 1e-3) / 1e6
+    v_p = bits / (np.mean(ms_p) * 1e-3) / 1e6
+    line = {
+        "metric": "info Mbit/s decoded, mixed batch (N 128-2048, rate 1/4-5/6, D 8/32/64) in one persistent launch",
+        "value": v_m, "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": float(np.mean(ms_m)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
+        "config": {"workload": "mixed batch: 25 codes (CRC-16) x D in {8,32,64}, L=8, Eb/N0 U[1.5,3.5]",
+                   "frames": B, "groups": len(groups), "parallelism": "single GPU"},
+        "plain_one_launch_per_config": {"value": v_p, "unit": "Mbit/s", "launches": len(groups),
+                                        "ms_per_step": float(np.mean(ms_p))},
+        "mixed_over_plain": v_m / v_p,
+        "outputs_equal": same, "fer": fer,
+    }
+    print(json.dumps(line))
+
+
+def serve_pool(seed, n_req, codes, pcs):
+    """A pool of requests of the mixed distribution (code, D), 1..256 frames each, LLRs
+    generated on the device with the library's encoder and copied to host memory."""
+    import torch
+
+    from paper_1809_03606_amd import channel
+    from paper_1809_03606_amd.serve import Request
+
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    pool = []
+    for rid in range(n_req):
+        c = int(rng.integers(len(codes)))
+        n, k = codes[c]
+        m = int(rng.integers(1, 257))
+        pay = channel.device_payload(torch, gen, m, k - 16, "cuda")
+        cw = torch.empty((m, n), dtype=torch.uint8, device="cuda")
+        pcs[c].encode_device(pay, cw)
+        ebs = torch.full((m,), float(rng.uniform(1.5, 3.5)), dtype=torch.float64, device="cuda")
+        llr = channel.device_llr_per_frame(torch, gen, cw, ebs, k / n).cpu().numpy()
+        pool.append(Request(rid=rid, code=c, D=int(rng.choice([8, 32, 64])), L=8, llr=llr))
+    return pool
+
+
+def run_serve(args):
+    """Poisson arrivals of requests (1..256 frames of one code / D from the mixed
+    distribution) at args.serve_load x the saturated capacity, admitted by device-memory
+    budget into 4 concurrent slots; reports latency percentiles and sustained payload bit/s."""
+    import copy
+
+    import torch
+
+    from paper_1809_03606_amd import binding, channel
+    from paper_1809_03606_amd.serve import GpuBackend, Server
+
+    torch.cuda.set_device(0)
+    codes = channel.mixed_codes()
+    pcs = [binding.PolarCode(n, k, 16, 2.0) for (n, k) in codes]
+    shapes = [(n, k - 16) for (n, k) in codes]
+    pool = serve_pool(5, 512, codes, pcs)
+    log("serve: pool of %d requests ready" % len(pool))
+    be = GpuBackend(pcs, n_slots=4, max_frames=8192)
+    # saturated capacity: the whole pool submitted at once
+    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=8192)
+    t0 = time.perf_counter()
+    for r in pool:
+        srv.submit(copy.copy(r))
+    srv.drain()
+    cap_s = time.perf_counter() - t0
+    frames = sum(r.frames for r in pool)
+    cap_fps = frames / cap_s
+    log("serve: saturated capacity %.0f frames/s (%.1f s)" % (cap_fps, cap_s))
+    # Poisson arrivals at the offered load for the run time
+    rng = np.random.default_rng(6)
+    rate = args.serve_load * cap_fps / (frames / len(pool))  # requests per second
+    arrivals, t, k = [], 0.0, 0
+    while t < args.serve_seconds:
+        t += float(rng.exponential(1.0 / rate))
+        r = copy.copy(pool[k % len(pool)])
+        r.rid = k
+        arrivals.append((t, r))
+        k += 1
+    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=8192)
+    log("serve: replaying %d requests over %.0f s" % (len(arrivals), args.serve_seconds))
+    rep = srv.run(arrivals)
+    line = {
+        "metric": "p50/p99 request latency and sustained info Mbit/s, continuous-batching server",
+        "value": rep["payload_mbps"], "unit": "Mbit/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": rep["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded BPSK/AWGN requests of the mixed distribution",
+        "config": {"workload": "serving: Poisson requests of 1-256 frames, mixed codes/D, "
+                               "4 slots, 1 GiB budget",
+                   "offered_load": args.serve_load, "capacity_frames_per_s": cap_fps,
+                   "requests": len(arrivals), "seconds": args.serve_seconds},
+        "latency_ms": {"p50": rep["latency_ms_p50"], "p99": rep["latency_ms_p99"],
+                       "mean": rep["latency_ms_mean"]},
+        "batches": rep["batches"], "max_concurrent_batches": be.max_concurrent,
     }
     print(json.dumps(line))
 

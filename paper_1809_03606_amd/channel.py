@@ -122,3 +122,14 @@ def mixed_draw(seed: int, B: int):
     D = np.asarray(MIXED_D)[g.integers(0, len(MIXED_D), size=B)]
     ebn0 = g.uniform(1.5, 3.5, size=B)
     return code.astype(np.int32), D.astype(np.int32), ebn0
+
+
+def device_llr_per_frame(torch, gen, codeword, ebn0_db, rate: float):
+    """As device_llr (binary32) with one Eb/N0 per frame (a float64 tensor of length B)."""
+    B, N = codeword.shape
+    n = torch.randn((B, N), generator=gen, dtype=torch.float64, device=codeword.device)
+    s2 = 1.0 / (2.0 * rate * torch.pow(10.0, ebn0_db / 10.0))
+    x = 1.0 - 2.0 * codeword.to(torch.float64)
+    y = x + torch.sqrt(s2)[:, None] * n
+    del n, x
+    return ((2.0 * y) / s2[:, None]).to(torch.float32)

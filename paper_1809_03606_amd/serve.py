@@ -1,0 +1,261 @@
+"""Continuous-batching decode server over the C-ABI.
+
+Requests (one code, one D and L, 1..256 frames each) arrive over time.  The server keeps a
+FIFO of waiting requests and several device slots (one HIP stream and one decoder context
+each).  Whenever a slot is free it admits waiting requests, oldest first, while their
+device footprint fits the free part of the memory budget, packs their LLRs into the slot's
+pinned staging buffer, copies them to the device and enqueues one mixed-batch decode
+(``scs_decode_mixed``) plus the copy of the results back; batches of different slots run
+concurrently on the GPU.  A request that arrives while others are decoding joins the next
+free slot: slots and budget are released as batches finish.
+
+Footprint of a request (bytes of device memory its frames hold while in flight): LLRs
+(4 N per frame), payload and status bytes, and the decoder's per-frame LDS state.  A
+request larger than the whole budget is rejected at submission.
+
+The backend interface (``submit`` / ``done`` / ``collect`` / ``free_slots``) is what the
+scheduler talks to, so the scheduling logic can be exercised with any object that
+implements it.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import binding
+
+
+def frame_state_bytes(N: int, D: int) -> int:
+    """On-chip decoder state of one frame (stack rows, L counters, alpha tree, spare)."""
+    W = N // 32 if N >= 32 else 1
+    return 4 * (D * W + (N + 3) // 4 + N + 64)
+
+
+def request_footprint(N: int, kp: int, D: int, frames: int) -> int:
+    return frames * (4 * N + kp + 1 + frame_state_bytes(N, D))
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    code: int            # index into the server's code list
+    D: int
+    L: int
+    llr: np.ndarray      # float32 [frames][N]
+    t_arrival: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    payload: np.ndarray | None = None  # uint8 [frames][kp]
+    status: np.ndarray | None = None   # uint8 [frames]
+    footprint: int = 0
+
+    @property
+    def frames(self) -> int:
+        return int(self.llr.shape[0])
+
+
+class AdmissionError(ValueError):
+    pass
+
+
+class GpuBackend:
+    """Device slots: a stream, a decoder context and pinned staging buffers each."""
+
+    def __init__(self, codes, n_slots: int = 4, max_frames: int = 4096, device: int = 0):
+        import torch
+
+        self.torch = torch
+        self.codes = codes  # list of binding.PolarCode
+        self.dev = torch.device("cuda", device)
+        maxN = max(c.N for c in codes)
+        maxkp = max(c.payload_bits for c in codes)
+        self.max_frames = max_frames
+        self.max_concurrent = 0  # most batches seen in flight at once
+        self.slots = []
+        for _ in range(n_slots):
+            s = {
+                "stream": torch.cuda.Stream(device=self.dev),
+                "ctx": binding.ScsContext(device),
+                "h_llr": torch.empty(max_frames * maxN, dtype=torch.float32, pin_memory=True),
+                "d_llr": torch.empty(max_frames * maxN, dtype=torch.float32, device=self.dev),
+                "d_pay": torch.empty(max_frames * maxkp, dtype=torch.uint8, device=self.dev),
+                "d_st": torch.empty(max_frames, dtype=torch.uint8, device=self.dev),
+                "h_pay": torch.empty(max_frames * maxkp, dtype=torch.uint8, pin_memory=True),
+                "h_st": torch.empty(max_frames, dtype=torch.uint8, pin_memory=True),
+                "event": None, "batch": None, "busy": False,
+            }
+            # size the context's plan buffers once, so that no submission has to grow them
+            big = max(range(len(codes)), key=lambda c: codes[c].N)
+            plan = np.zeros(max_frames, binding.FRAME_DTYPE)
+            plan["code"], plan["D"], plan["L"] = big, 1, 1
+            binding.scs_mixed_prepare(s["ctx"].handle, [c.handle for c in codes], plan, s["stream"])
+            s["stream"].synchronize()
+            self.slots.append(s)
+
+    def free_slots(self):
+        return [i for i, s in enumerate(self.slots) if not s["busy"]]
+
+    def submit(self, slot: int, reqs):
+        torch = self.torch
+        s = self.slots[slot]
+        n = sum(r.frames for r in reqs)
+        if n > self.max_frames:
+            raise AdmissionError("batch of %d frames exceeds the slot size %d" % (n, self.max_frames))
+        frames = np.zeros(n, binding.FRAME_DTYPE)
+        hl = s["h_llr"].numpy()
+        f = lo = lo_o = 0
+        spans = []
+        for r in reqs:
+            code = self.codes[r.code]
+            m = r.frames
+            hl[lo:lo + m * code.N] = r.llr.reshape(-1)
+            frames[f:f + m]["code"] = r.code
+            frames[f:f + m]["D"] = r.D
+            frames[f:f + m]["L"] = r.L
+            frames[f:f + m]["llr_off"] = lo + np.arange(m) * code.N
+            frames[f:f + m]["out_off"] = lo_o + np.arange(m) * code.payload_bits
+            spans.append((f, lo_o, m, code.payload_bits))
+            f += m
+            lo += m * code.N
+            lo_o += m * code.payload_bits
+        st = s["stream"]
+        with torch.cuda.stream(st):
+            s["d_llr"][:lo].copy_(s["h_llr"][:lo], non_blocking=True)
+            binding.scs_decode_mixed(s["ctx"].handle, [c.handle for c in self.codes], frames,
+                                     binding.SCS_LLR_F32, s["d_llr"], s["d_pay"], s["d_st"], None, st)
+            s["h_pay"][:lo_o].copy_(s["d_pay"][:lo_o], non_blocking=True)
+            s["h_st"][:n].copy_(s["d_st"][:n], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        s.update(event=ev, batch=(reqs, spans), busy=True)
+        self.max_concurrent = max(self.max_concurrent, sum(x["busy"] for x in self.slots))
+
+    def done(self, slot: int) -> bool:
+        s = self.slots[slot]
+        return s["busy"] and s["event"].query()
+
+    def collect(self, slot: int):
+        s = self.slots[slot]
+        reqs, spans = s["batch"]
+        hp, hs = s["h_pay"].numpy(), s["h_st"].numpy()
+        for r, (f, lo_o, m, kp) in zip(reqs, spans):
+            r.payload = hp[lo_o:lo_o + m * kp].reshape(m, kp).copy()
+            r.status = hs[f:f + m].copy()
+        s.update(event=None, batch=None, busy=False)
+        return reqs
+
+
+class Server:
+    """FIFO admission under a device-memory budget, continuous batching over the slots."""
+
+    def __init__(self, backend, code_shapes, budget_bytes: int = 512 << 20,
+                 max_batch_frames: int = 4096, clock=time.perf_counter):
+        self.backend = backend
+        self.shapes = code_shapes  # list of (N, kp)
+        self.budget = int(budget_bytes)
+        self.max_batch_frames = int(max_batch_frames)
+        self.clock = clock
+        self.waiting = collections.deque()
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.completed = []
+        self.batches = 0
+
+    def footprint(self, r: Request) -> int:
+        N, kp = self.shapes[r.code]
+        return request_footprint(N, kp, r.D, r.frames)
+
+    def submit(self, r: Request, now: float | None = None):
+        r.footprint = self.footprint(r)
+        if r.footprint > self.budget or r.frames > self.max_batch_frames:
+            raise AdmissionError("request %d needs %d bytes / %d frames, budget %d bytes / %d frames"
+                                 % (r.rid, r.footprint, r.frames, self.budget, self.max_batch_frames))
+        r.t_arrival = self.clock() if now is None else now
+        self.waiting.append(r)
+
+    def cancel(self, rid: int) -> bool:
+        """Drop a request that is still waiting; a request already on the device finishes."""
+        for r in list(self.waiting):
+            if r.rid == rid:
+                self.waiting.remove(r)
+                return True
+        return False
+
+    def step(self) -> int:
+        """Retire finished batches, then admit waiting requests into free slots.  Returns the
+        number of requests completed by this call."""
+        now = self.clock()
+        finished = 0
+        for slot in range(len(self.backend.slots)):
+            if self.backend.done(slot):
+                for r in self.backend.collect(slot):
+                    r.t_done = now
+                    self.in_use -= r.footprint
+                    self.completed.append(r)
+                    finished += 1
+        for slot in self.backend.free_slots():
+            if not self.waiting:
+                break
+            batch, frames, need = [], 0, 0
+            while self.waiting:
+                r = self.waiting[0]
+                if self.in_use + need + r.footprint > self.budget:
+                    break
+                if frames + r.frames > self.max_batch_frames:
+                    break
+                batch.append(self.waiting.popleft())
+                frames += r.frames
+                need += r.footprint
+            if not batch:
+                break
+            for r in batch:
+                r.t_admit = now
+            self.in_use += need
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.backend.submit(slot, batch)
+            self.batches += 1
+        return finished
+
+    def busy(self) -> bool:
+        return bool(self.waiting) or any(s["busy"] for s in self.backend.slots)
+
+    def drain(self, timeout_s: float = 120.0):
+        t0 = self.clock()
+        while self.busy():
+            if self.clock() - t0 > timeout_s:
+                raise TimeoutError("server did not drain in %.0f s" % timeout_s)
+            if self.step() == 0:
+                time.sleep(0.0002)
+
+    def run(self, arrivals, poll_s: float = 0.0002):
+        """arrivals: list of (offset_seconds, Request), ascending offsets.  Replays them in
+        real time against the backend and drains the server."""
+        t0 = self.clock()
+        k = 0
+        while k < len(arrivals) or self.busy():
+            now = self.clock() - t0
+            while k < len(arrivals) and arrivals[k][0] <= now:
+                self.submit(arrivals[k][1], now=t0 + arrivals[k][0])
+                k += 1
+            if self.step() == 0:
+                time.sleep(poll_s)
+        return self.report()
+
+    def report(self):
+        lat = np.array([r.t_done - r.t_arrival for r in self.completed])
+        if lat.size == 0:
+            return {"requests": 0}
+        t_first = min(r.t_arrival for r in self.completed)
+        t_last = max(r.t_done for r in self.completed)
+        bits = sum(r.frames * self.shapes[r.code][1] for r in self.completed)
+        frames = sum(r.frames for r in self.completed)
+        return {"requests": len(self.completed), "frames": frames, "batches": self.batches,
+                "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+                "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+                "latency_ms_mean": float(lat.mean() * 1e3),
+                "payload_mbps": bits / max(t_last - t_first, 1e-9) / 1e6,
+                "span_s": t_last - t_first, "peak_budget_bytes": self.peak_in_use,
+                "budget_bytes": self.budget}
