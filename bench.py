@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
                     help="lanes per frame (0: the library's choice)")
-    ap.add_argument("--workload", choices=("sweep", "mixed", "serve"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "mixed", "serve", "fixed"), default="sweep",
                     help="sweep: PC(1024,512) headline; mixed: 25 codes / 3 depths in one launch; "
                          "serve: Poisson requests through the continuous-batching server")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -117,7 +117,13 @@ def main():
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
             sys.exit(2)
-        (run_mixed if args.workload == "mixed" else run_serve)(args)
+        {"mixed": run_mixed, "serve": run_serve}[args.workload](args)
+        return
+    if args.workload == "fixed":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        run_fixed(args)
         return
     if args.gpus != 1:
         print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
@@ -407,6 +413,92 @@ def run_mixed(args):
                                         "ms_per_step": float(np.mean(ms_p))},
         "mixed_over_plain": v_m / v_p,
         "outputs_equal": same, "fer": fer,
+    }
+    print(json.dumps(line))
+
+
+def wilson(k, n, z=1.959964):
+    """95% Wilson score interval of a binomial proportion."""
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    den = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return (float(c - h), float(c + h))
+
+
+def run_fixed(args):
+    """Fixed point at 2 dB: the same 10^6 noisy frames decoded with binary32 LLRs and with
+    int8 LLRs q = clamp(rint(T y)) (int8 tree, int16 path metric); FER of both with 95%
+    intervals, the quantiser scale T chosen by a sweep on the first 200,000 frames, and the
+    throughput of both decoders."""
+    import torch
+
+    from paper_1809_03606_amd import binding, channel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    B, eb, kp = args.frames, 2.0, K - CRC
+    code = binding.PolarCode(N, K, CRC, 2.0)
+    ctx = binding.ScsContext(0)
+    stream = torch.cuda.Stream(device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(SEED * 1000 + 2)
+    pay = channel.device_payload(torch, gen, B, kp, dev)
+    y = torch.empty((B, N), dtype=torch.float64, device=dev)  # channel output, for quantising
+    llr = torch.empty((B, N), dtype=torch.float32, device=dev)
+    s2 = channel.sigma2(eb, K / N)
+    chunk = 1 << 17
+    for lo in range(0, B, chunk):
+        hi = min(B, lo + chunk)
+        cw = torch.empty((hi - lo, N), dtype=torch.uint8, device=dev)
+        code.encode_device(pay[lo:hi], cw)
+        nz = channel.device_noise(torch, gen, hi - lo, N, dev)
+        llr[lo:hi] = channel.device_llr_from_noise(torch, cw, nz, eb, K / N, "f32")
+        y[lo:hi] = (1.0 - 2.0 * cw.to(torch.float64)) + np.sqrt(s2) * nz
+        del cw, nz
+    torch.cuda.synchronize()
+    out = torch.empty((B, kp), dtype=torch.uint8, device=dev)
+    st = torch.empty((B,), dtype=torch.uint8, device=dev)
+
+    def decode(x, n):
+        dt = binding.SCS_LLR_F32 if x.dtype == torch.float32 else binding.SCS_LLR_I8
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        binding.scs_decode_batch(ctx.handle, code.handle, D, L, dt, x, n, out, st, None, stream)
+        b.record(stream)
+        stream.synchronize()
+        errs = int((out[:n] != pay[:n]).any(dim=1).sum().item())
+        return errs, a.elapsed_time(b)
+
+    # quantiser scale: 200k frames per candidate
+    ns = min(B, 200_000)
+    sweep = {}
+    for T in (2.0, 4.0, 8.0, 16.0):
+        q = torch.clamp(torch.round(T * y[:ns]), -127, 127).to(torch.int8)
+        sweep[T] = decode(q, ns)[0] / ns
+        log("fixed: T=%g FER %.4f on %d frames" % (T, sweep[T], ns))
+    T = min(sweep, key=lambda t: (sweep[t], t))
+    q = torch.empty((B, N), dtype=torch.int8, device=dev)
+    for lo in range(0, B, chunk):
+        hi = min(B, lo + chunk)
+        q[lo:hi] = torch.clamp(torch.round(T * y[lo:hi]), -127, 127).to(torch.int8)
+    decode(llr, B)
+    decode(q, B)  # warm-up
+    e32, ms32 = decode(llr, B)
+    e8, ms8 = decode(q, B)
+    line = {
+        "metric": "FER of int8/int16 fixed-point SCS vs binary32 at 2 dB, and throughput",
+        "value": B * kp / (ms8 * 1e-3) / 1e6, "unit": "Mbit/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": ms8, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i8",
+        "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
+        "config": {"workload": "fixed point PC(1024,512)+CRC16 D=32 L=8 Eb/N0 2.0 dB",
+                   "frames": B, "quantiser_scale": T, "scale_sweep_fer": sweep},
+        "fer_i8": e8 / B, "fer_i8_ci95": wilson(e8, B),
+        "fer_f32": e32 / B, "fer_f32_ci95": wilson(e32, B),
+        "f32_payload_mbps": B * kp / (ms32 * 1e-3) / 1e6,
     }
     print(json.dumps(line))
 

@@ -133,3 +133,19 @@ def device_llr_per_frame(torch, gen, codeword, ebn0_db, rate: float):
     y = x + torch.sqrt(s2)[:, None] * n
     del n, x
     return ((2.0 * y) / s2[:, None]).to(torch.float32)
+
+
+def device_noise(torch, gen, B: int, N: int, device):
+    return torch.randn((B, N), generator=gen, dtype=torch.float64, device=device)
+
+
+def device_llr_from_noise(torch, codeword, n, ebn0_db: float, rate: float, dtype: str = "f32",
+                          scale: float = 8.0):
+    """Same arithmetic as bpsk_awgn_llr / bpsk_awgn_i8 on device tensors (binary64, rounded
+    once), so that host and device give identical values for identical noise."""
+    s2 = sigma2(ebn0_db, rate)
+    x = 1.0 - 2.0 * codeword.to(torch.float64)
+    y = x + math.sqrt(s2) * n
+    if dtype == "f32":
+        return ((2.0 * y) / s2).to(torch.float32)
+    return torch.clamp(torch.round(scale * y), -127, 127).to(torch.int8)

@@ -1,0 +1,86 @@
+"""Full-size batches in the launch configuration the benchmark times (10^6 frames of
+PC(1024,512)+CRC-16, D=32, L=8, one launch), checked on a sample of frames against the
+oracle.  The batch is generated on the device; for the sampled frames the payload and the
+noise are copied back, encoded with the oracle's encoder and passed through the channel on
+the host, and those host LLRs (which must equal the device LLRs bit for bit) are what the
+oracle decodes."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from cases import THREADS
+from paper_1809_03606_amd import channel
+
+pytestmark = pytest.mark.gpu
+
+N, K, CRC, D, L = 1024, 512, 16, 32, 8
+FRAMES = 1_000_000
+SAMPLE = 240
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _full(cuda, ebn0, dtype, seed):
+    from paper_1809_03606_amd import binding
+
+    torch = cuda
+    code = binding.PolarCode(N, K, CRC, 2.0)
+    info = oracle.construct(N, K, 2.0)
+    assert (code.info_mask == info).all()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    kp = K - CRC
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(FRAMES, SAMPLE, replace=False))
+    pay = channel.device_payload(torch, gen, FRAMES, kp, "cuda")
+    llr = torch.empty((FRAMES, N), dtype=torch.float32 if dtype == "f32" else torch.int8, device="cuda")
+    s_noise = np.zeros((SAMPLE, N))
+    chunk = 1 << 17
+    for lo in range(0, FRAMES, chunk):
+        hi = min(FRAMES, lo + chunk)
+        cw = torch.empty((hi - lo, N), dtype=torch.uint8, device="cuda")
+        code.encode_device(pay[lo:hi], cw)
+        nz = channel.device_noise(torch, gen, hi - lo, N, "cuda")
+        llr[lo:hi] = channel.device_llr_from_noise(torch, cw, nz, ebn0, K / N, dtype)
+        sel = sample[(sample >= lo) & (sample < hi)]
+        if sel.size:
+            s_noise[np.searchsorted(sample, sel)] = nz[torch.from_numpy(sel - lo).cuda()].cpu().numpy()
+        del cw, nz
+    out = torch.empty((FRAMES, kp), dtype=torch.uint8, device="cuda")
+    st = torch.empty((FRAMES,), dtype=torch.uint8, device="cuda")
+    ctx = binding.ScsContext(0)
+    _say("gpu: full-size %s batch at %.1f dB" % (dtype, ebn0))
+    ctx.decode(code, D, L, llr, out, st)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(sample).cuda()
+    g_pay, g_st = out[idx].cpu().numpy(), st[idx].cpu().numpy()
+    d_llr = llr[idx].cpu().numpy()
+    # host reconstruction of the sampled inputs, independent of the library
+    s_pay = pay[idx].cpu().numpy()
+    cw_h = oracle.encode_batch(info, CRC, s_pay)
+    if dtype == "f32":
+        h_llr = channel.bpsk_awgn_llr(cw_h, s_noise, ebn0, K / N)
+        mode = oracle.F32
+    else:
+        h_llr = channel.bpsk_awgn_i8(cw_h, s_noise, ebn0, K / N)
+        mode = oracle.FIX
+    assert np.array_equal(h_llr.view(np.uint8), d_llr.view(np.uint8))
+    rp, rs, _ = oracle.scs_decode_batch(mode, info, CRC, D, L, h_llr, threads=THREADS)
+    assert np.array_equal(rp, g_pay) and np.array_equal(rs, g_st)
+    fer = float((out != pay).any(dim=1).float().mean().item())
+    _say("full-size %s %.1f dB: FER %.4f" % (dtype, ebn0, fer))
+    return fer
+
+
+@pytest.mark.parametrize("ebn0", [1.0, 2.0])
+def test_gpu_full_size_float32_sampled_against_oracle(cuda, ebn0):
+    _full(cuda, ebn0, "f32", seed=20 + int(ebn0 * 10))
+
+
+def test_gpu_full_size_fixed_point_sampled_against_oracle(cuda):
+    _full(cuda, 2.0, "i8", seed=30)
