@@ -56,7 +56,12 @@ def parse():
                     help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
-                    help="lanes per frame (0: the library's choice)")
+                    help="lanes per frame (0: the autotuner's choice, see --tune)")
+    ap.add_argument("--wpb", type=int, default=0, choices=(0, 1, 2, 4),
+                    help="wavefronts per workgroup (0: the autotuner's choice)")
+    ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
+                    help="launch-shape autotuner: use the cached choice or tune once (auto), "
+                         "always re-tune (force), or use the library's defaults (off)")
     ap.add_argument("--workload", choices=("sweep", "mixed", "serve", "fixed"), default="sweep",
                     help="sweep: PC(1024,512) headline; mixed: 25 codes / 3 depths in one launch; "
                          "serve: Poisson requests through the continuous-batching server")
@@ -143,7 +148,22 @@ def main():
     kp = K - CRC
 
     code = binding.PolarCode(N, K, CRC, 2.0)
-    ctx = binding.ScsContext(0, args.lanes)
+    ctx = binding.ScsContext(0, args.lanes, args.wpb)
+    launch_shape = {"lanes_per_frame": args.lanes, "waves_per_block": args.wpb, "source": "flags"}
+    if not (args.lanes or args.wpb) and args.tune != "off":
+        from paper_1809_03606_amd import tune
+
+        entry = None if args.tune == "force" else tune.apply(ctx, code, D, L, args.dtype)
+        source = "cache"
+        if entry is None:
+            t0 = time.time()
+            entry = tune.tune(code, D, L, args.dtype)
+            tune.apply(ctx, code, D, L, args.dtype)
+            source = "tuned in %.1f s" % (time.time() - t0)
+        launch_shape = {"lanes_per_frame": entry["lanes_per_frame"],
+                        "waves_per_block": entry["waves_per_block"], "source": source,
+                        "candidates_ms": entry["candidates_ms"]}
+        log("launch shape: %s" % launch_shape)
     stream = torch.cuda.Stream(device=dev)
     llr_dtype = binding.SCS_LLR_F32 if args.dtype == "f32" else binding.SCS_LLR_I8
 
@@ -242,8 +262,9 @@ def main():
     peak = PEAK_LANE_OPS / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                 "frac": achieved / peak, "traffic": measured_traffic(B),
-                "kernel": "scs_uniform_kernel<10,f32>" if args.dtype == "f32" else
-                          "scs_uniform_kernel<10,i8>",
+                "kernel": ("scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
+                           else "scs_rows_kernel<%d>" % launch_shape["lanes_per_frame"])
+                          + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
                 "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch}
 
     # -- CPU oracle on a bounded sample of the same frames -----------------------------
@@ -284,7 +305,8 @@ def main():
         "config": {"workload": "SCS sweep PC(1024,512)+CRC16 D=32 L=8 Eb/N0 1.0-3.0 dB",
                    "N": N, "K": K, "crc_bits": CRC, "D": D, "L": L,
                    "ebn0_db": points, "frames_per_point": B, "global_batch": B * len(points),
-                   "launches_per_step": len(points), "parallelism": "single GPU"},
+                   "launches_per_step": len(points), "parallelism": "single GPU",
+                   "launch_shape": launch_shape},
         "latency": {"launch_ms_p50": float(np.percentile(all_ms, 50)),
                     "launch_ms_p99": float(np.percentile(all_ms, 99))},
         "per_point": {str(k): v for k, v in per_point.items()},

@@ -98,6 +98,11 @@ void scs_ctx_destroy(scs_ctx* ctx);
  * not depend on this setting.  Errors: POLAR_EINVAL for any other value. */
 int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame);
 
+/* Wavefronts per workgroup of the decoder launches: 1, 2 or 4, or 0 for the library's
+ * choice (4, fewer when their LDS state would exceed 64 KB).  A launch never uses more
+ * than fit.  Results do not depend on this setting.  Errors: POLAR_EINVAL otherwise. */
+int scs_ctx_set_waves_per_block(scs_ctx* ctx, int32_t waves_per_block);
+
 /* Per-frame counters (optional output of the decoders), one record per frame. */
 typedef struct {
   uint32_t iterations;  /* leaf estimates (path extensions) */

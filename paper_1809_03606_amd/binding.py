@@ -25,7 +25,7 @@ SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
-           "scs_ctx_last_error", "polar_strerror")
+           "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
                 "drops", "prunes")
@@ -79,12 +79,13 @@ def lib():
             L.scs_mixed_launch.argtypes = [vp, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
             L.scs_ctx_set_lanes.argtypes = [vp, i32]
+            L.scs_ctx_set_waves_per_block.argtypes = [vp, i32]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
-                      "scs_ctx_last_error"):
+                      "scs_ctx_set_waves_per_block", "scs_ctx_last_error"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -201,6 +202,11 @@ def scs_ctx_set_lanes(ctx: int, lanes_per_frame: int):
     _check(lib().scs_ctx_set_lanes(ctx, int(lanes_per_frame)), "scs_ctx_set_lanes")
 
 
+def scs_ctx_set_waves_per_block(ctx: int, waves_per_block: int):
+    _check(lib().scs_ctx_set_waves_per_block(ctx, int(waves_per_block)),
+           "scs_ctx_set_waves_per_block")
+
+
 def scs_ctx_last_error(ctx: int) -> int:
     return int(lib().scs_ctx_last_error(ctx))
 
@@ -245,11 +251,17 @@ class PolarCode:
 
 
 class ScsContext:
-    def __init__(self, device: int = 0, lanes_per_frame: int = 0):
+    def __init__(self, device: int = 0, lanes_per_frame: int = 0, waves_per_block: int = 0):
         self.handle = scs_ctx_create(device)
         self.device = device
         if lanes_per_frame:
             scs_ctx_set_lanes(self.handle, lanes_per_frame)
+        if waves_per_block:
+            scs_ctx_set_waves_per_block(self.handle, waves_per_block)
+
+    def configure(self, lanes_per_frame: int = 0, waves_per_block: int = 0):
+        scs_ctx_set_lanes(self.handle, lanes_per_frame)
+        scs_ctx_set_waves_per_block(self.handle, waves_per_block)
 
     def decode(self, code: PolarCode, D: int, L: int, llr_dev, payload_dev, status_dev,
                stats_dev=None, stream=None):

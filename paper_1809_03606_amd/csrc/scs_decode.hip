@@ -657,6 +657,7 @@ int waves_per_block(int N, int D) {
 struct scs_ctx {
   int device = 0;
   int lanes = 0;  // lanes per frame: 0 = automatic, else 16, 32 or 64
+  int wpb = 0;    // wavefronts per workgroup: 0 = automatic, else 1, 2 or 4
   int last_error = POLAR_OK;
   int cus = 0;    // compute units of the device
   std::mutex mu;
@@ -745,6 +746,15 @@ int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame) {
   return POLAR_OK;
 }
 
+int scs_ctx_set_waves_per_block(scs_ctx* ctx, int32_t waves_per_block) {
+  if (!ctx) return POLAR_EINVAL;
+  if (waves_per_block != 0 && waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return POLAR_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->wpb = waves_per_block;
+  return POLAR_OK;
+}
+
 int scs_ctx_last_error(scs_ctx* ctx) {
   if (!ctx) return POLAR_EINVAL;
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -777,7 +787,8 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
     a.L = L;
     a.dtype = llr_dtype;
     a.waves_per_block = 1;
-    while (a.waves_per_block < 4 &&
+    const int cap = ctx->wpb ? ctx->wpb : 4;
+    while (a.waves_per_block < cap &&
            polarscs::rows_lds_bytes(code->N, D, G, a.waves_per_block * 2) <= kMaxLdsPerBlock)
       a.waves_per_block *= 2;
     a.llr = llr_dev;
@@ -794,7 +805,8 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
     }
     return POLAR_OK;
   }
-  const int wpb = waves_per_block(code->N, D);
+  int wpb = waves_per_block(code->N, D);
+  if (ctx->wpb && ctx->wpb < wpb) wpb = ctx->wpb;
   const int wave_words = lds_words_per_wave(code->N, D);
   const size_t lds = (size_t)wpb * wave_words * 4;
   const int64_t blocks = (n_frames + wpb - 1) / wpb;
@@ -902,7 +914,7 @@ int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8
   if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
   hipStream_t s = (hipStream_t)hip_stream;
   const int ww = ctx->plan_wave_words;
-  int wpb = 4;
+  int wpb = ctx->wpb ? ctx->wpb : 4;
   while (wpb > 1 && (size_t)wpb * ww * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * ww * 4;
   const bool st = stats_dev != nullptr;

@@ -106,3 +106,20 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_waves_per_block_knob_rejects_bad_arguments(lib):
+    assert lib.scs_ctx_set_waves_per_block(None, 2) == binding.POLAR_EINVAL
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    from paper_1809_03606_amd import tune
+
+    code = binding.PolarCode(1024, 512, 16)
+    k = tune.key("gfx950", code, 32, 8, "f32")
+    assert k == "gfx950:N1024:K512:crc16:D32:L8:f32"
+    path = str(tmp_path / "sub" / "tune.json")
+    assert tune.load(path) == {}
+    tune.save({k: {"lanes_per_frame": 32, "waves_per_block": 2}}, path)
+    assert tune.load(path)[k]["waves_per_block"] == 2
+    assert (64, 4) in tune.CANDIDATES and len(tune.CANDIDATES) == 9

@@ -1,0 +1,49 @@
+"""GPU: the launch-shape autotuner and the waves-per-workgroup knob.  Every launch shape
+must give the oracle's bits; the tuner must store a choice among its candidates and
+``apply`` must configure a context with it."""
+import numpy as np
+import pytest
+
+from cases import assert_parity, gpu_decode, make_frames, oracle_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("wpb", [1, 2, 4])
+def test_every_launch_shape_matches_oracle(cuda, lanes, wpb):
+    from paper_1809_03606_amd.binding import PolarCode
+
+    N, K, crc, D, L = 512, 256, 16, 32, 8
+    info, pay, llr = make_frames(N, K, crc, 1.5, 53, seed=97)
+    ref = oracle_decode(info, crc, D, L, llr)
+    print("gpu: launch shape lanes=%d wpb=%d" % (lanes, wpb), flush=True)
+    got = gpu_decode(cuda, PolarCode(N, K, crc, 2.0), D, L, llr, lanes=lanes, wpb=wpb)
+    assert_parity(got, ref, "lanes=%d wpb=%d" % (lanes, wpb))
+
+
+def test_tuner_stores_and_applies(cuda, tmp_path):
+    from paper_1809_03606_amd import binding, tune
+
+    code = binding.PolarCode(256, 128, 16)
+    path = str(tmp_path / "tune.json")
+    print("gpu: tuner on PC(256,128)", flush=True)
+    entry = tune.tune(code, 16, 8, "f32", frames=4096, reps=1, path=path)
+    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in tune.CANDIDATES
+    assert len(entry["candidates_ms"]) == len(tune.CANDIDATES)
+    ctx = binding.ScsContext(0)
+    got = tune.apply(ctx, code, 16, 8, "f32", path=path)
+    assert got["lanes_per_frame"] == entry["lanes_per_frame"]
+    assert tune.apply(ctx, binding.PolarCode(128, 64, 0), 16, 8, "f32", path=path) is None
+    # the configured context still decodes to the oracle's bits
+    info, pay, llr = make_frames(256, 128, 16, 2.0, 40, seed=5)
+    ref = oracle_decode(info, 16, 16, 8, llr)
+    torch = cuda
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(llr).to(dev)
+    out = torch.empty((40, code.payload_bits), dtype=torch.uint8, device=dev)
+    st = torch.empty((40,), dtype=torch.uint8, device=dev)
+    ctx.decode(code, 16, 8, x, out, st)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert np.array_equal(out.cpu().numpy(), ref[0]) and np.array_equal(st.cpu().numpy(), ref[1])
