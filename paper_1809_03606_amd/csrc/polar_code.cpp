@@ -144,6 +144,20 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_d
       c->crc_unit[p] = crc16_payload(e.data(), kp);
       e[p] = 0;
     }
+    // syndrome share of information rank r: payload bits contribute their remainder, the
+    // CRC bits (most significant first) the register bit they must cancel
+    const int nbytes = (N + 7) / 8;
+    std::vector<uint16_t> share(N, 0);
+    for (int r = 0; r < K; ++r)
+      share[c->info_pos[r]] = r < kp ? c->crc_unit[r] : (uint16_t)(1u << (crc_bits - 1 - (r - kp)));
+    c->crc_syn.assign((size_t)nbytes * 256, 0);
+    for (int b = 0; b < nbytes; ++b)
+      for (int v = 1; v < 256; ++v) {
+        const int j = __builtin_ctz((unsigned)v);
+        const int pos = 8 * b + j;
+        c->crc_syn[(size_t)b * 256 + v] =
+            (uint16_t)(c->crc_syn[(size_t)b * 256 + (v & (v - 1))] ^ (pos < N ? share[pos] : 0));
+      }
   }
   *out = c;
   return POLAR_OK;

@@ -16,6 +16,11 @@ struct polar_code {
   uint32_t info_words[64] = {};  // info mask, bit j of word w = position 32 w + j
   uint16_t info_prefix[64] = {}; // number of information positions before word w
   std::vector<uint16_t> crc_unit; // CRC remainder of the unit payload vector e_p, p < K - crc
+  // CRC check of a decided bit vector by bytes: entry 256 b + v is the xor, over the
+  // information bits set in value v of byte b (positions 8b..8b+7), of each bit's share of
+  // the CRC syndrome (payload bit: its unit remainder; CRC bit: its place in the register).
+  // A vector passes the check when the xor over its bytes is 0.  Empty without a CRC.
+  std::vector<uint16_t> crc_syn;
   int32_t payload_bits() const { return K - crc; }
   int32_t words() const { return N >= 32 ? N / 32 : 1; }
 };

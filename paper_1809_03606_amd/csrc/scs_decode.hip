@@ -200,6 +200,38 @@ inline int lds_words_per_wave(int N, int D) {
   return D * W + (N + 3) / 4 + N + kWave;
 }
 
+// Path keys: one 64-bit word, path metric (a non-negative value whose 32-bit pattern
+// orders like the value) in the high half and key_lo in the low half, so that unsigned
+// order is (PM ascending, PL descending, creation order ascending).  kNone is above every
+// key (a path metric never has the all-ones pattern).
+constexpr uint64_t kNone = ~0ull;
+
+__device__ __forceinline__ uint64_t make_key(uint32_t pm, uint32_t lo) {
+  return ((uint64_t)pm << 32) | lo;
+}
+
+// CRC check of a complete path (Section 2.2.5): the CRC register has no initial value and
+// no final xor, so it is linear in the information bits and the check is the xor of
+// per-bit contributions; `tab` holds, for every byte of the bit vector and every byte
+// value, the xor of the contributions of its information bits (zero for a valid word).
+// Lane w holds bits 32w..32w+31 of the path.  Returns the wave-wide xor (0: check passed).
+__device__ __forceinline__ uint32_t crc_syndrome(const uint16_t* __restrict__ tab, uint32_t row,
+                                                 int lane, int W, int nbytes) {
+  uint32_t acc = 0u;
+  if (lane < W) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 4 * lane + k;
+      if (b < nbytes) acc ^= tab[b * 256 + ((row >> (8 * k)) & 0xFFu)];
+    }
+  }
+  acc ^= dpp<0xB1>(acc);
+  acc ^= dpp<0x4E>(acc);
+  acc ^= dpp<0x141>(acc);  // row_half_mirror: lane i pairs with the other quad
+  acc ^= dpp<0x140>(acc);  // row_mirror: the other half-row
+  return readlane(acc, 0) ^ readlane(acc, 16) ^ readlane(acc, 32) ^ readlane(acc, 48);
+}
+
 // One frame, one wavefront.  `lds` is this wave's private region of
 // lds_words_per_wave(N, D) words.
 template <int LOGN, class TR, bool STATS>
@@ -222,23 +254,19 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
   lds_order();
 
-  // stack: slot s = lane s
-  uint32_t s_pm = 0u, s_lo = key_lo(N, 0, 0u), s_crc = 0u;
-  int s_pl = 0;
+  // stack: slot s = lane s holds one key; its length is N - (low word >> kSeqBits)
+  uint64_t s_key = make_key(0u, key_lo(N, 0, 0u));
   uint64_t vmask = 1ull;  // the empty path in slot 0
   const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
   uint32_t next_seq = 1;
 
-  // fast path: the first child of the last extension ("candidate") wins whenever its key
-  // is below a lower bound on every other live key
-  bool have_cand = false;
-  int cand_slot = 0, cand_pl = 0;
-  uint32_t cand_hi = 0u, cand_lo = 0u, cand_crc = 0u;
-  uint32_t lb_hi = 0u, lb_lo = 0u;
-  // exact worst live key, when known
-  bool have_max = false;
+  // fast path: the first child of the last extension ("candidate", kNone if none) wins
+  // whenever its key is below lb, a lower bound on every other live key
+  uint64_t cand = kNone, lb = 0ull;
+  int cand_slot = 0;
+  // exact worst live key, kNone when unknown
+  uint64_t maxk = kNone;
   int max_slot = 0;
-  uint32_t max_hi = 0u, max_lo = 0u;
 
   // the path held in the tree: its length when alpha was last computed, its decided bits
   int wl = -1;
@@ -253,212 +281,179 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   // at most L N extensions and L completions: an unreachable bound that still guarantees
   // every wavefront leaves the loop
   uint32_t budget = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
-  bool done = false;
-  while (!done) {
+  for (;;) {
     if (budget == 0u) {
       st = 0u;
-      done = true;
-    } else if (vmask == 0ull) {
-      st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
-      out = fb;
-      done = true;
+      break;
+    }
+    --budget;
+    // ---- the best path -------------------------------------------------------------
+    int p;
+    uint64_t pk;
+    bool cont;
+    if (cand < lb) {
+      p = cand_slot;
+      pk = cand;
+      cont = true;
     } else {
-      --budget;
-      // ---- the best path -----------------------------------------------------------
-      int p = 0, pl = 0;
-      uint32_t ppm = 0u, plo = 0u, pcrc = 0u;
-      bool cont = false;
-      if (have_cand && key_less(cand_hi, cand_lo, lb_hi, lb_lo)) {
-        p = cand_slot;
-        pl = cand_pl;
-        ppm = cand_hi;
-        plo = cand_lo;
-        pcrc = cand_crc;
-        cont = true;
-      } else {
-        const bool live = (vmask >> lane) & 1ull;
-        const uint32_t kh = live ? s_pm : 0xFFFFFFFFu;
-        const uint32_t mh = wave_min(kh);
-        const uint64_t tie = ballot(kh == mh) & vmask;
-        if (__builtin_popcountll(tie) == 1) {
-          p = __builtin_ctzll(tie);
-          const uint32_t k2 = (live && lane != p) ? s_pm : 0xFFFFFFFFu;
-          lb_hi = wave_min(k2);
-        } else {
-          const uint32_t kl = ((tie >> lane) & 1ull) ? s_lo : 0xFFFFFFFFu;
-          const uint32_t ml = wave_min(kl);
-          p = __builtin_ctzll(ballot(kl == ml) & tie);
-          lb_hi = mh;
-        }
-        lb_lo = 0u;
-        pl = (int)readlane((uint32_t)s_pl, p);
-        plo = readlane(s_lo, p);
-        ppm = mh;
-        pcrc = readlane(s_crc, p);
-        cont = have_cand && plo == cand_lo;
+      if (vmask == 0ull) {
+        st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
+        out = fb;
+        break;
       }
-      vmask &= ~(1ull << p);
-      if (have_max && max_slot == p) have_max = false;
-      have_cand = false;
+      const bool live = (vmask >> lane) & 1ull;
+      const uint32_t kh = live ? (uint32_t)(s_key >> 32) : 0xFFFFFFFFu;
+      const uint32_t mh = wave_min(kh);
+      const uint64_t tie = ballot(kh == mh) & vmask;
+      uint32_t ml;
+      if (__builtin_popcountll(tie) == 1) {
+        p = __builtin_ctzll(tie);
+        ml = readlane((uint32_t)s_key, p);
+        lb = (uint64_t)wave_min(lane != p ? kh : 0xFFFFFFFFu) << 32;
+      } else {
+        const uint32_t kl = ((tie >> lane) & 1ull) ? (uint32_t)s_key : 0xFFFFFFFFu;
+        ml = wave_min(kl);
+        p = __builtin_ctzll(ballot(kl == ml) & tie);
+        lb = make_key(mh, ml + 1u);  // the other tied keys have larger low words
+      }
+      pk = make_key(mh, ml);
+      cont = pk == cand;
+    }
+    vmask &= ~(1ull << p);
+    if (max_slot == p) maxk = kNone;
+    cand = kNone;
+    const int i = N - (int)((uint32_t)pk >> kSeqBits);  // length of the best path
 
-      if (pl == N) {
-        // a complete path: the CRC decides (Section 2.2.5)
-        if constexpr (STATS) ++n_cp;
-        const uint32_t row = lane < W ? rows[p * W + wq] : 0u;
-        if (!use_crc || pcrc == 0u) {
-          st = SCS_STATUS_OK;
-          out = row;
-          done = true;
+    if (i == N) {
+      // a complete path: the CRC decides (Section 2.2.5)
+      if constexpr (STATS) ++n_cp;
+      const uint32_t row = lane < W ? rows[p * W + wq] : 0u;
+      if (!use_crc || crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
+        st = SCS_STATUS_OK;
+        out = row;
+        break;
+      }
+      if (!have_fb) {
+        fb = row;
+        have_fb = true;
+      }
+      if (++fails >= L) {
+        st = SCS_STATUS_FALLBACK;
+        out = fb;
+        break;
+      }
+      continue;
+    }
+
+    // ---- extend path p by leaf i ---------------------------------------------------
+    if constexpr (STATS) {
+      ++n_it;
+      n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
+    }
+    // L counter of length i; lane 0 adds, the others add 0 to their dummy word
+    const uint32_t old = atomicAdd(lane == 0 ? &cnt32[i >> 2] : &dummy[lane],
+                                   lane == 0 ? (1u << (8 * (i & 3))) : 0u);
+
+    int top;
+    if (cont) {
+      top = __builtin_ctz((uint32_t)i);  // the SC schedule continues (i = wl + 1 > 0)
+    } else {
+      if constexpr (STATS) ++n_sw;
+      const uint32_t nu = lane < W ? rows[p * W + wq] : 0u;
+      int A = LOGN, d = 0;
+      if (wl >= 0) {
+        const int lim = wl < i ? wl : i;
+        const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
+        const uint64_t bx = ballot(x != 0u);
+        if (bx == 0ull) {
+          d = lim;
         } else {
-          if (!have_fb) {
-            fb = row;
-            have_fb = true;
-          }
-          if (++fails >= L) {
-            st = SCS_STATUS_FALLBACK;
-            out = fb;
-            done = true;
-          }
+          const int w = __builtin_ctzll(bx);
+          d = w * 32 + __builtin_ctz(readlane(x, w));
+        }
+        A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
+      }
+      const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
+      top = (A > Bm ? A : Bm) - 1;
+      if (top < 0) top = 0;
+      ucur = nu;
+    }
+    if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
+    const uint32_t a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+
+    // ---- leaf decision and children (eq. scest, eq. PMupd) ---------------------------
+    const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
+    const bool h = TR::hd(a0);
+    const uint32_t ppm = (uint32_t)(pk >> 32);
+    const uint32_t pm1 = TR::pm_add(ppm, TR::mag(a0));  // metric against the decision
+    const uint32_t lo0 = key_lo(N, i + 1, next_seq);
+    const uint64_t k0 = make_key((!info && h) ? pm1 : ppm, lo0);
+    next_seq += info ? 2u : 1u;
+    const int wi = i >> 5;
+    const uint32_t bitm = 1u << (i & 31);
+    // bit i of the tree's path may hold a stale bit of the slot's previous occupant
+    ucur = (lane == wi) ? ((ucur & ~bitm) | (info && h ? bitm : 0u)) : ucur;
+    *(lane == wi ? &rows[p * W + wi] : &dummy[lane]) = ucur;
+    s_key = (lane == p) ? k0 : s_key;
+    vmask |= 1ull << p;
+    if (k0 > maxk) {  // never true while the worst key is unknown
+      maxk = k0;
+      max_slot = p;
+    }
+
+    if (info) {
+      // the flipped child, against the decision: metric pm1, next sequence number
+      const uint64_t k1 = make_key(pm1, lo0 + 1u);
+      int t = -1;
+      if (__builtin_popcountll(vmask) < D) {
+        t = __builtin_ctzll(~vmask & dmask);
+        if (k1 > maxk) {
+          maxk = k1;
+          max_slot = t;
         }
       } else {
-        // ---- extend path p by leaf i -------------------------------------------------
-        const int i = pl;
-        if constexpr (STATS) {
-          ++n_it;
-          n_sc += (i == 0) ? (uint32_t)(N - 1) : ((2u << __builtin_ctz((uint32_t)i)) - 1u);
+        if (maxk == kNone) {
+          const bool lv = (vmask >> lane) & 1ull;
+          const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
+          const uint32_t Mh = wave_max(xh);
+          const uint64_t tq = ballot(xh == Mh) & vmask;
+          uint32_t Ml;
+          if (__builtin_popcountll(tq) == 1) {
+            max_slot = __builtin_ctzll(tq);
+            Ml = readlane((uint32_t)s_key, max_slot);
+          } else {
+            const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
+            Ml = wave_max(xl);
+            max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
+          }
+          maxk = make_key(Mh, Ml);
         }
-        // L counter of length i; lane 0 adds, the others add 0 to their dummy word
-        const uint32_t old = atomicAdd(lane == 0 ? &cnt32[i >> 2] : &dummy[lane],
-                                       lane == 0 ? (1u << (8 * (i & 3))) : 0u);
-
-        int top = 0;
-        if (cont) {
-          top = __builtin_ctz((uint32_t)i);  // the SC schedule continues (i = wl + 1 > 0)
+        if (k1 < maxk) {
+          t = max_slot;
+          maxk = kNone;
+          if constexpr (STATS) ++n_ev;
         } else {
-          if constexpr (STATS) ++n_sw;
-          const uint32_t nu = lane < W ? rows[p * W + wq] : 0u;
-          int A = LOGN, d = 0;
-          if (wl < 0) {
-            A = LOGN;
-            d = 0;
-          } else {
-            const int lim = wl < i ? wl : i;
-            const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
-            const uint64_t bx = ballot(x != 0u);
-            if (bx == 0ull) {
-              d = lim;
-            } else {
-              const int w = __builtin_ctzll(bx);
-              d = w * 32 + __builtin_ctz(readlane(x, w));
-            }
-            A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
-          }
-          const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
-          top = (A > Bm ? A : Bm) - 1;
-          if (top < 0) top = 0;
-          ucur = nu;
+          if constexpr (STATS) ++n_dr;
         }
-        if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
-        const uint32_t a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
-
-        // ---- leaf decision and children (eq. scest, eq. PMupd) -----------------------
-        const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
-        const bool h = TR::hd(a0);
-        const uint32_t pm1 = TR::pm_add(ppm, TR::mag(a0));  // metric against the decision
-        const uint32_t b0 = (info && h) ? 1u : 0u;
-        const uint32_t pm0 = (!info && h) ? pm1 : ppm;
-        const uint32_t crc0 = info ? crc_step(pcrc, b0) : pcrc;
-        const uint32_t seq0 = next_seq;
-        next_seq += info ? 2u : 1u;
-        const uint32_t lo0 = key_lo(N, i + 1, seq0);
-        const int wi = i >> 5;
-        const uint32_t bitm = 1u << (i & 31);
-        ucur = (lane == wi) ? ((ucur & ~bitm) | (b0 ? bitm : 0u)) : ucur;
-        *(lane == wi ? &rows[p * W + wi] : &dummy[lane]) = ucur;
-        if (lane == p) {
-          s_pm = pm0;
-          s_lo = lo0;
-          s_pl = i + 1;
-          s_crc = crc0;
-        }
-        vmask |= 1ull << p;
-        if (have_max && key_less(max_hi, max_lo, pm0, lo0)) {
-          max_hi = pm0;
-          max_lo = lo0;
-          max_slot = p;
-        }
-
-        if (info) {
-          // the flipped child: its CRC register differs by the polynomial (feedback flips)
-          const uint32_t crc1 = crc0 ^ 0x1021u;
-          const uint32_t lo1 = lo0 + 1u;  // next sequence number, same length
-          int t = -1;
-          if (__builtin_popcountll(vmask) < D) {
-            t = __builtin_ctzll(~vmask & dmask);
-            if (have_max && key_less(max_hi, max_lo, pm1, lo1)) {
-              max_hi = pm1;
-              max_lo = lo1;
-              max_slot = t;
-            }
-          } else {
-            if (!have_max) {
-              const bool lv = (vmask >> lane) & 1ull;
-              const uint32_t xh = lv ? s_pm : 0u;
-              const uint32_t Mh = wave_max(xh);
-              const uint64_t tq = ballot(xh == Mh) & vmask;
-              int q;
-              if (__builtin_popcountll(tq) == 1) {
-                q = __builtin_ctzll(tq);
-              } else {
-                const uint32_t xl = ((tq >> lane) & 1ull) ? s_lo : 0u;
-                const uint32_t Ml = wave_max(xl);
-                q = __builtin_ctzll(ballot(xl == Ml) & tq);
-              }
-              max_slot = q;
-              max_hi = Mh;
-              max_lo = readlane(s_lo, q);
-              have_max = true;
-            }
-            if (key_less(pm1, lo1, max_hi, max_lo)) {
-              t = max_slot;
-              have_max = false;
-              if constexpr (STATS) ++n_ev;
-            } else {
-              if constexpr (STATS) ++n_dr;
-            }
-          }
-          if (t >= 0) {
-            *(lane < W ? &rows[t * W + wq] : &dummy[lane]) = ucur ^ (lane == wi ? bitm : 0u);
-            if (lane == t) {
-              s_pm = pm1;
-              s_lo = lo1;
-              s_pl = i + 1;
-              s_crc = crc1;
-            }
-            vmask |= 1ull << t;
-            if (key_less(pm1, lo1, lb_hi, lb_lo)) {
-              lb_hi = pm1;
-              lb_lo = lo1;
-            }
-          }
-        }
-        lds_order();
-
-        // L-counter pruning
-        if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
-          if constexpr (STATS) ++n_pr;
-          vmask &= ~ballot(s_pl <= i);
-          have_max = false;
-        }
-        wl = i;
-        have_cand = true;
-        cand_slot = p;
-        cand_pl = i + 1;
-        cand_hi = pm0;
-        cand_lo = lo0;
-        cand_crc = crc0;
+      }
+      if (t >= 0) {
+        *(lane < W ? &rows[t * W + wq] : &dummy[lane]) = ucur ^ (lane == wi ? bitm : 0u);
+        s_key = (lane == t) ? k1 : s_key;
+        vmask |= 1ull << t;
+        if (k1 < lb) lb = k1;
       }
     }
+    lds_order();
+
+    // L-counter pruning: drop every path of length <= i
+    if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
+      if constexpr (STATS) ++n_pr;
+      vmask &= ~ballot(((uint32_t)s_key >> kSeqBits) >= (uint32_t)(N - i));
+      maxk = kNone;
+    }
+    wl = i;
+    cand = k0;
+    cand_slot = p;
   }
 
   // output: payload = the first K - r information bits of the output path
@@ -654,6 +649,38 @@ int waves_per_block(int N, int D) {
 
 }  // namespace
 
+// Device copies of a code's host tables (CRC unit remainders for the encoder, the CRC
+// syndrome table for the decoders), one per code, device and table, uploaded on first use
+// and kept until the process ends: a code's tables are a few to 128 KB.
+enum CodeTable { kTabCrcUnit = 0, kTabCrcSyn = 1 };
+
+int device_table(const polar_code* code, CodeTable which, const uint16_t** out) {
+  static std::mutex mu;
+  static std::unordered_map<uint64_t, uint16_t*> tables;  // key: (uid * 64 + device) * 2 + table
+  *out = nullptr;
+  const std::vector<uint16_t>& src = which == kTabCrcUnit ? code->crc_unit : code->crc_syn;
+  if (code->crc == 0 || src.empty()) return POLAR_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EDEVICE;
+  const uint64_t key = (code->uid * 64 + (uint64_t)dev) * 2 + (uint64_t)which;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = tables.find(key);
+  if (it != tables.end()) {
+    *out = it->second;
+    return POLAR_OK;
+  }
+  uint16_t* tab = nullptr;
+  const size_t bytes = sizeof(uint16_t) * src.size();
+  if (hipMalloc(&tab, bytes) != hipSuccess) return POLAR_ENOMEM;
+  if (hipMemcpy(tab, src.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(tab);
+    return POLAR_EDEVICE;
+  }
+  tables[key] = tab;
+  *out = tab;
+  return POLAR_OK;
+}
+
 struct scs_ctx {
   int device = 0;
   int lanes = 0;  // lanes per frame: 0 = automatic, else 16, 32 or 64
@@ -776,7 +803,8 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   if (code->logn < 1 || code->logn > 11) return POLAR_EUNSUPPORTED;
   if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
 
-  const CodeArgs args = make_args(code);
+  CodeArgs args = make_args(code);
+  if (const int e = device_table(code, kTabCrcSyn, &args.crc_tab)) return e;
   hipStream_t s = (hipStream_t)hip_stream;
   const int G = choose_lanes(ctx, code->N, D);
   if (G != 64) {
@@ -890,7 +918,10 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
   CodeArgs* hc = (CodeArgs*)ctx->h_stage;
   scs_frame* hf = (scs_frame*)(ctx->h_stage + nc * sizeof(CodeArgs));
   int32_t* ho = (int32_t*)(ctx->h_stage + nc * sizeof(CodeArgs) + nf * sizeof(scs_frame));
-  for (int32_t c = 0; c < n_codes; ++c) hc[c] = make_args(codes[c]);
+  for (int32_t c = 0; c < n_codes; ++c) {
+    hc[c] = make_args(codes[c]);
+    if (const int e = device_table(codes[c], kTabCrcSyn, &hc[c].crc_tab)) return e;
+  }
   if (n_frames) {
     std::memcpy(hf, frames_host, (size_t)n_frames * sizeof(scs_frame));
     std::memcpy(ho, order.data(), (size_t)n_frames * sizeof(int32_t));
@@ -965,32 +996,13 @@ int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
   if (!code || B < 0) return POLAR_EINVAL;
   if (B == 0) return POLAR_OK;
   if (!codeword_dev || (!payload_dev && code->payload_bits() > 0)) return POLAR_EINVAL;
-  // The CRC unit table rides in a small device buffer owned per code and device.
-  static std::mutex mu;
-  static std::unordered_map<uint64_t, uint16_t*> tables;  // key: uid * 64 + device
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EDEVICE;
-  uint16_t* tab = nullptr;
-  if (code->crc) {
-    std::lock_guard<std::mutex> g(mu);
-    const uint64_t key = code->uid * 64 + (uint64_t)dev;
-    auto it = tables.find(key);
-    if (it == tables.end()) {
-      const size_t bytes = sizeof(uint16_t) * (size_t)std::max(1, code->payload_bits());
-      if (hipMalloc(&tab, bytes) != hipSuccess) return POLAR_ENOMEM;
-      if (hipMemcpy(tab, code->crc_unit.data(), sizeof(uint16_t) * code->crc_unit.size(),
-                    hipMemcpyHostToDevice) != hipSuccess)
-        return POLAR_EDEVICE;
-      tables[key] = tab;
-    } else {
-      tab = it->second;
-    }
-  }
+  const uint16_t* tab = nullptr;
+  if (const int e = device_table(code, kTabCrcUnit, &tab)) return e;
   const CodeArgs args = make_args(code);
   const int64_t blocks = (B + 3) / 4;
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
   hipLaunchKernelGGL(encode_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
-                     args, (const uint16_t*)tab, payload_dev, codeword_dev, B);
+                     args, tab, payload_dev, codeword_dev, B);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EDEVICE;
 }
 

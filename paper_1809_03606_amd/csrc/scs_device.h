@@ -15,6 +15,7 @@ struct CodeArgs {
   int32_t N, K, crc, logn, W, kp;
   uint32_t info[64];
   uint16_t pre[64];
+  const uint16_t* crc_tab;  // device copy of polar_code::crc_syn (null without a CRC)
 };
 
 inline CodeArgs make_args(const polar_code* c) {
