@@ -194,11 +194,12 @@ struct FrameJob {
   int D, L;
 };
 
-// LDS words per wave: decided-bit rows, per-length counters, alpha tree, dummy words.
-inline int lds_words_per_wave(int N, int D) {
-  const int W = N >= 32 ? N / 32 : 1;
-  return D * W + (N + 3) / 4 + N + kWave;
-}
+// LDS words per wave: per-length counters, alpha tree, dummy words.  The decided-bit
+// rows of the stack live in lane-private memory (see decode_frame), so the LDS share of a
+// frame does not depend on D.
+inline int lds_words_per_wave(int N, int /*D*/) { return (N + 3) / 4 + N + kWave; }
+
+constexpr int kMaxD = 64;  // stack slots are lanes
 
 // Path keys: one 64-bit word, path metric (a non-negative value whose 32-bit pattern
 // orders like the value) in the high half and key_lo in the low half, so that unsigned
@@ -244,11 +245,14 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   const int D = job.D, L = job.L;
   const bool use_crc = code.crc != 0;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
-  uint32_t* rows = lds;                // D x W words: decided bits of slot s in row s
-  uint32_t* cnt32 = lds + D * W;       // N bytes: extensions per length
+  // decided bits of slot s: word w in prow[s] of lane w.  Every access is by the lane
+  // that owns the word, so the array is private to the lane (scratch memory, cached) and
+  // needs no ordering across lanes; entry kMaxD takes the stores of lanes that must not
+  // store.
+  uint32_t prow[kMaxD + 1];
+  uint32_t* cnt32 = lds;               // N bytes: extensions per length
   uint32_t* al = cnt32 + (N + 3) / 4;  // N - 1 words: alpha stages 0 .. n-1
   uint32_t* dummy = al + N;            // kWave words: stores of lanes that must not store
-  const int wq = lane < W ? lane : W - 1;
 
   const uint32_t infow = lane < W ? code.info[lane] : 0u;
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
@@ -327,7 +331,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     if (i == N) {
       // a complete path: the CRC decides (Section 2.2.5)
       if constexpr (STATS) ++n_cp;
-      const uint32_t row = lane < W ? rows[p * W + wq] : 0u;
+      const uint32_t row = lane < W ? prow[p] : 0u;
       if (!use_crc || crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
         st = SCS_STATUS_OK;
         out = row;
@@ -359,7 +363,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       top = __builtin_ctz((uint32_t)i);  // the SC schedule continues (i = wl + 1 > 0)
     } else {
       if constexpr (STATS) ++n_sw;
-      const uint32_t nu = lane < W ? rows[p * W + wq] : 0u;
+      const uint32_t nu = lane < W ? prow[p] : 0u;
       int A = LOGN, d = 0;
       if (wl >= 0) {
         const int lim = wl < i ? wl : i;
@@ -393,7 +397,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     const uint32_t bitm = 1u << (i & 31);
     // bit i of the tree's path may hold a stale bit of the slot's previous occupant
     ucur = (lane == wi) ? ((ucur & ~bitm) | (info && h ? bitm : 0u)) : ucur;
-    *(lane == wi ? &rows[p * W + wi] : &dummy[lane]) = ucur;
+    prow[lane == wi ? p : kMaxD] = ucur;
     s_key = (lane == p) ? k0 : s_key;
     vmask |= 1ull << p;
     if (k0 > maxk) {  // never true while the worst key is unknown
@@ -437,7 +441,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
         }
       }
       if (t >= 0) {
-        *(lane < W ? &rows[t * W + wq] : &dummy[lane]) = ucur ^ (lane == wi ? bitm : 0u);
+        prow[lane < W ? t : kMaxD] = ucur ^ (lane == wi ? bitm : 0u);
         s_key = (lane == t) ? k1 : s_key;
         vmask |= 1ull << t;
         if (k1 < lb) lb = k1;
