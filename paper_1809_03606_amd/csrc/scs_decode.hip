@@ -186,6 +186,62 @@ __device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t u,
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
+// f-stages LAM .. 1 of a continuing schedule, each stored for later leaves, then stage 0.
+template <int LAM, class TR, bool STATS>
+__device__ __forceinline__ uint32_t f_chain(uint32_t x, uint32_t* al, uint32_t* dummy, int lane,
+                                            uint32_t& fg) {
+  if constexpr (LAM >= 1) {
+    x = TR::f(x, xor_lane<(1 << LAM)>(x));
+    *(lane < (1 << LAM) ? &al[(1 << LAM) - 1 + lane] : &dummy[lane]) = x;
+    if constexpr (STATS) fg += 1u << LAM;
+    return f_chain<LAM - 1, TR, STATS>(x, al, dummy, lane, fg);
+  } else {
+    if constexpr (STATS) fg += 1u;
+    return TR::f(x, xor_lane<1>(x));
+  }
+}
+
+// The SC schedule continuing at leaf i with ctz(i) = K <= SMALL: stage K is a g-node (bit K
+// of i is 1, its left sibling is the block [i - 2^K, i)) and every stage below it is an
+// f-node (those bits of i are 0), so the chain is straight-line code.  Returns the leaf LLR.
+template <int K, int LOGN, class TR, bool STATS>
+__device__ __forceinline__ uint32_t cont_chain(int i, uint32_t u,
+                                               const typename TR::In* __restrict__ root,
+                                               uint32_t* al, uint32_t* dummy, int lane,
+                                               uint32_t& fg) {
+  constexpr int nin = 2 << K;  // values of stage K + 1
+  const int q = lane < nin ? lane : nin - 1;
+  uint32_t x;
+  if constexpr (K + 1 == LOGN)
+    x = TR::load(root, q);
+  else
+    x = al[nin - 1 + q];
+  const uint32_t m = sibling_small<K>(u, i - (1 << K));
+  x = TR::g(x, xor_lane<(1 << K)>(x), (m >> (lane & 31)) & 1u);
+  if constexpr (K >= 1) {
+    *(lane < (1 << K) ? &al[(1 << K) - 1 + lane] : &dummy[lane]) = x;
+    if constexpr (STATS) fg += 1u << K;
+    x = f_chain<K - 1, TR, STATS>(x, al, dummy, lane, fg);
+  } else {
+    if constexpr (STATS) fg += 1u;
+  }
+  lds_order();
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+template <int K, int LOGN, class TR, bool STATS>
+__device__ __forceinline__ uint32_t cont_dispatch(int top, int i, uint32_t u,
+                                                  const typename TR::In* __restrict__ root,
+                                                  uint32_t* al, uint32_t* dummy, int lane,
+                                                  uint32_t& fg) {
+  if constexpr (K < Layout<LOGN>::SMALL) {
+    if (top == K) return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg);
+    return cont_dispatch<K + 1, LOGN, TR, STATS>(top, i, u, root, al, dummy, lane, fg);
+  } else {
+    return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg);
+  }
+}
+
 struct FrameJob {
   const void* llr;   // N values of the frame
   uint8_t* payload;  // kp output bits
@@ -382,8 +438,13 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       if (top < 0) top = 0;
       ucur = nu;
     }
-    if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
-    const uint32_t a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+    uint32_t a0;
+    if (cont && top <= LY::SMALL) {
+      a0 = cont_dispatch<0, LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+    } else {
+      if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
+      a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+    }
 
     // ---- leaf decision and children (eq. scest, eq. PMupd) ---------------------------
     const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
