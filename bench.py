@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
     ap.add_argument("--points", type=str, default=",".join(str(p) for p in POINTS))
     ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
-    ap.add_argument("--cpu-sample", type=int, default=2000,
+    ap.add_argument("--cpu-sample", type=int, default=40000,
                     help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
@@ -69,6 +69,13 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured saturated capacity")
     ap.add_argument("--mixed-frames", type=int, default=2_000_000)
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the HBM traffic record from four rocprofv3 --pmc output folders "
+                         "(decoder FETCH_SIZE, decoder WRITE_SIZE, 1 GiB copy FETCH_SIZE and "
+                         "WRITE_SIZE) and exit; runs on the CPU")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "BENCH_JSON", "OUT_MD"),
+                    help="summarise a rocprofv3 --kernel-trace --stats folder of a bench run "
+                         "into markdown and exit; runs on the CPU")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -102,6 +109,115 @@ def measured_traffic(frames_per_launch: int):
     return rec["hbm_bytes_per_frame"] * frames_per_launch
 
 
+COPY_BYTES = 1 << 30
+DECODER = "scs_uniform_kernel"
+
+
+def _csv_rows(folder: str, suffix: str):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True)):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _counter_kib(folder: str, counter: str, kernel: str, exclude: str = "\0"):
+    """Per-dispatch values (KiB) of `counter` for the dispatches whose name contains
+    `kernel` and not `exclude`, summed over the counter's instances."""
+    per = {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        name = r["Kernel_Name"]
+        if kernel in name and exclude not in name and r["Counter_Name"] == counter:
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return [per[k] for k in sorted(per, key=int)]
+
+
+def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_000_000):
+    """HBM bytes per decoder launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each
+    scaled by what the same counter reads for a device copy of COPY_BYTES."""
+    # the timed launch only: the counter launch (", true>" variant) also writes statistics
+    dec_f = _counter_kib(fetch_dir, "FETCH_SIZE", DECODER, ", true>")
+    dec_w = _counter_kib(write_dir, "WRITE_SIZE", DECODER, ", true>")
+    cp_f = max(_counter_kib(cfetch_dir, "FETCH_SIZE", "copyBuffer"))  # the device copy
+    cp_w = max(_counter_kib(cwrite_dir, "WRITE_SIZE", "copyBuffer"))
+    ff = COPY_BYTES / (cp_f * 1024.0)
+    wf = COPY_BYTES / (cp_w * 1024.0)
+    rd = float(np.mean(dec_f)) * 1024.0 * ff
+    wr = float(np.mean(dec_w)) * 1024.0 * wf
+    rec = {
+        "kernel": DECODER + "<10,f32> (64 lanes per frame)",
+        "kernel_source_hash": kernel_source_hash(),
+        "workload": "PC(1024,512)+CRC16, D=32, L=8, Eb/N0 2.0 dB, %d frames per launch" % frames,
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+            "--points 2.0 --steps 1 --warmup 0 --cpu-sample 0",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+            "--points 2.0 --steps 1 --warmup 0 --cpu-sample 0",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+            "--calibrate-copy %d" % COPY_BYTES,
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+            "--calibrate-copy %d" % COPY_BYTES,
+            "python bench.py --traffic-record <fetch> <write> <copy fetch> <copy write>"],
+        "raw_kib_per_dispatch": {"decoder_fetch_size": dec_f, "decoder_write_size": dec_w,
+                                 "copy_1GiB_fetch_size": cp_f, "copy_1GiB_write_size": cp_w},
+        "calibration": {"fetch_factor": ff, "write_factor": wf,
+                        "note": "a 1 GiB device copy reads 1 GiB and writes 1 GiB; each counter "
+                                "is scaled by the ratio of that to what it reports for the copy"},
+        "hbm_read_bytes_per_launch": rd,
+        "hbm_write_bytes_per_launch": wr,
+        "hbm_bytes_per_frame": (rd + wr) / frames,
+        "algorithmic_bytes_per_frame": 4 * N + (K - CRC) + 1,
+    }
+    with open(TRAFFIC_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"traffic_record": TRAFFIC_RECORD, "hbm_bytes_per_frame": rec["hbm_bytes_per_frame"]}))
+
+
+def write_trace_summary(trace_dir, bench_json, out_md):
+    """Markdown summary of a kernel trace of `python bench.py --cpu-sample 0`: per-kernel
+    statistics, and the decoder's mean duration beside bench.py's own HIP-event mean."""
+    rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    per = {}
+    for r in rows:
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        short = name.split("(")[0].strip()
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+        per.setdefault(short[:90], []).append(d)
+    total = sum(sum(v) for v in per.values())
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    lines = ["# Kernel trace: SCS decoder, PC(1024,512)+CRC-16 sweep", "",
+             "Command (from the repository root on one MI355X):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
+             "python bench.py --cpu-sample 0", "",
+             "Workload: N=1024, K=512 (496 payload + 16 CRC), D=32, L=8, Eb/N0 1.0/1.5/2.0/2.5/3.0 "
+             "dB, %d frames per point, launch shape %s.  Decoder launches: one counter launch "
+             "per point (stats variant), %d warmup and %d timed steps of one launch per point.  "
+             "The CPU-oracle sample is off so that its small launches do not enter the average."
+             % (b["config"]["frames_per_point"], b["config"].get("launch_shape"), b["warmup"],
+                b["steps"]), "",
+             "| kernel | calls | average ms | min ms | max ms | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:8]:
+        lines.append("| %s | %d | %.3f | %.3f | %.3f | %.2f%% |" % (
+            k, len(v), np.mean(v), min(v), max(v), 100.0 * sum(v) / total))
+    dec = [d for k, v in per.items() if DECODER in k for d in v]
+    timed = [d for k, v in per.items() if DECODER in k and ", true>" not in k for d in v]
+    lines += ["", "Decoder mean over all %d launches (points mixed): %.1f ms.  Without the counter "
+              "launches (%d warmup + timed launches): %.1f ms.  bench.py's HIP-event mean over its "
+              "timed launches: %.1f ms (`roofline.mean_launch_ms`); bench value %.1f Mbit/s." % (
+                  len(dec), np.mean(dec), len(timed), np.mean(timed) if timed else float("nan"),
+                  b["roofline"]["mean_launch_ms"], b["value"]),
+              "", "Per point (bench.py, HIP events): " + ", ".join(
+                  "%s dB %.0f ms" % (k, v["launch_ms"]) for k, v in b["per_point"].items()) + "."]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def calibrate_copy(nbytes: int):
     import torch
 
@@ -117,6 +233,12 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
+    if args.trace_summary:
+        write_trace_summary(*args.trace_summary)
         return
     if args.workload in ("mixed", "serve"):
         if args.gpus != 1:

@@ -62,6 +62,14 @@ def lib():
             if not os.path.exists(_LIB_PATH):
                 raise RuntimeError("libpolarscs.so is not built: run `python -m "
                                    "paper_1809_03606_amd.build` (no CPU fallback exists)")
+            # PyTorch ships its own HIP runtime and asks for it by an unversioned name, so
+            # loading this library first would put a second runtime into the process (device
+            # buffers of one are not usable by the other).  Loaded after torch, the library's
+            # libamdhip64.so.7 resolves to the copy torch already mapped.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(_LIB_PATH)
             vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
             L.polar_construct.argtypes = [i32, i32, i32, dbl, ctypes.POINTER(vp)]

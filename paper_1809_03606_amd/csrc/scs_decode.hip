@@ -714,6 +714,12 @@ int waves_per_block(int N, int D) {
 
 }  // namespace
 
+// The HIP runtime keeps the last error of any call in the thread until it is read, and the
+// process may share the runtime with other libraries (PyTorch loads its own copy under the
+// same soname).  Launch sites read and drop whatever an earlier call left there, so that
+// the check after a launch reports that launch alone.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // Device copies of a code's host tables (CRC unit remainders for the encoder, the CRC
 // syndrome table for the decoders), one per code, device and table, uploaded on first use
 // and kept until the process ends: a code's tables are a few to 128 KB.
@@ -904,6 +910,7 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   const size_t lds = (size_t)wpb * wave_words * 4;
   const int64_t blocks = (n_frames + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
+  clear_stale_error();
   if (llr_dtype == SCS_LLR_F32) {
     auto k = uniform_kernel_for<TrF32>(code->logn, stats_dev != nullptr);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
@@ -1025,6 +1032,7 @@ int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8
     per_cu = 1;
   const int64_t need = ((int64_t)ctx->plan_frames + wpb - 1) / wpb;
   const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, need);
+  clear_stale_error();
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, ctx->d_counter);
   if (llr_dtype == SCS_LLR_F32) {
     auto k = st ? scs_mixed_kernel<TrF32, true> : scs_mixed_kernel<TrF32, false>;
@@ -1066,6 +1074,7 @@ int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
   const CodeArgs args = make_args(code);
   const int64_t blocks = (B + 3) / 4;
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
+  clear_stale_error();
   hipLaunchKernelGGL(encode_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
                      args, tab, payload_dev, codeword_dev, B);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EDEVICE;

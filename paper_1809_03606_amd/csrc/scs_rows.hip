@@ -722,6 +722,7 @@ hipError_t launch_t(const polarscs::RowsLaunch& a) {
   const int64_t waves = (a.n_frames + FR - 1) / FR;
   const int64_t blocks = (waves + a.waves_per_block - 1) / a.waves_per_block;
   const size_t lds = (size_t)a.waves_per_block * wave_words * 4;
+  (void)hipGetLastError();  // drop an error left by an earlier call of another library
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * a.waves_per_block), lds, a.stream,
                      a.code, a.D, a.L, (const typename TR::In*)a.llr, a.n_frames, a.payload,
                      a.status, a.stats, fw);

@@ -5,8 +5,12 @@ frame (64: one frame per wavefront; 32 / 16: two / four frames per wavefront) ti
 wavefronts per workgroup (1, 2, 4) -- on a sample batch of noisy frames at a
 representative Eb/N0, and keeps the fastest.  Results go to a JSON cache keyed by device
 architecture, N, K, CRC bits, D, L and LLR type (default file: $POLARSCS_TUNE_CACHE or
-~/.cache/polarscs/tune.json), and ``apply`` configures a decoder context from it.  The
-decoded bits do not depend on the launch shape; only the time does.
+~/.cache/polarscs/tune.json), and ``apply`` configures a decoder context from it.  Entries
+shipped with the package (``tuned.json``, written by this module's command line on an
+MI355X) answer when the user cache has none.  The decoded bits do not depend on the launch
+shape; only the time does.
+
+    python -m paper_1809_03606_amd.tune --N 1024 --K 512 --crc 16 --D 32 --L 8 --dtype f32
 """
 from __future__ import annotations
 
@@ -17,6 +21,7 @@ import time
 from . import binding, channel
 
 CANDIDATES = [(lanes, wpb) for lanes in (64, 32, 16) for wpb in (4, 2, 1)]
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
 def cache_path() -> str:
@@ -35,12 +40,21 @@ def key(arch: str, code, D: int, L: int, dtype: str) -> str:
     return "%s:N%d:K%d:crc%d:D%d:L%d:%s" % (arch, code.N, code.K, code.crc_bits, D, L, dtype)
 
 
-def load(path: str | None = None) -> dict:
+def _read(path: str) -> dict:
     try:
-        with open(path or cache_path()) as fh:
+        with open(path) as fh:
             return json.load(fh)
     except (OSError, ValueError):
         return {}
+
+
+def load(path: str | None = None) -> dict:
+    """Entries of `path`, or of the user cache over the shipped entries."""
+    if path:
+        return _read(path)
+    entries = _read(SHIPPED)
+    entries.update(_read(cache_path()))
+    return entries
 
 
 def save(entries: dict, path: str | None = None):
@@ -94,7 +108,7 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
     entry = {"lanes_per_frame": lanes, "waves_per_block": wpb, "ms": times[best],
              "candidates_ms": times, "frames": frames, "ebn0_db": ebn0_db,
              "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
-    entries = load(path)
+    entries = _read(path or cache_path())
     entries[key(_arch(torch), code, D, L, dtype)] = entry
     save(entries, path)
     ctx.close()
@@ -109,3 +123,29 @@ def apply(ctx, code, D: int, L: int, dtype: str = "f32", path: str | None = None
     if entry:
         ctx.configure(entry["lanes_per_frame"], entry["waves_per_block"])
     return entry
+
+
+def main(argv=None):
+    import argparse
+
+    from . import binding
+
+    ap = argparse.ArgumentParser(description="time the decoder's launch shapes, keep the best")
+    ap.add_argument("--N", type=int, required=True)
+    ap.add_argument("--K", type=int, required=True)
+    ap.add_argument("--crc", type=int, default=16)
+    ap.add_argument("--D", type=int, required=True)
+    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
+    ap.add_argument("--ebn0", type=float, default=2.0)
+    ap.add_argument("--frames", type=int, default=65536)
+    ap.add_argument("--out", default=None, help="cache file (default: the user cache)")
+    a = ap.parse_args(argv)
+    code = binding.PolarCode(a.N, a.K, a.crc, 2.0)
+    entry = tune(code, a.D, a.L, a.dtype, ebn0_db=a.ebn0, frames=a.frames, path=a.out,
+                 verbose=True)
+    print(json.dumps(entry))
+
+
+if __name__ == "__main__":
+    main()

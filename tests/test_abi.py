@@ -123,3 +123,17 @@ def test_tune_cache_roundtrip(tmp_path):
     tune.save({k: {"lanes_per_frame": 32, "waves_per_block": 2}}, path)
     assert tune.load(path)[k]["waves_per_block"] == 2
     assert (64, 4) in tune.CANDIDATES and len(tune.CANDIDATES) == 9
+
+
+def test_library_shares_pytorchs_hip_runtime():
+    """Loading the library before PyTorch must not map a second HIP runtime (device buffers
+    of one runtime are not usable by the other)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1809_03606_amd import binding\n"
+            "binding.lib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len(set(l.split()[-1] for l in maps if 'libamdhip64' in l)))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"

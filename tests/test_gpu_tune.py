@@ -47,3 +47,24 @@ def test_tuner_stores_and_applies(cuda, tmp_path):
     torch.cuda.synchronize()
     ctx.close()
     assert np.array_equal(out.cpu().numpy(), ref[0]) and np.array_equal(st.cpu().numpy(), ref[1])
+
+
+def test_tuner_command_line_in_a_fresh_process(cuda, tmp_path):
+    """The tuner as its own process: its first library call comes right after PyTorch's
+    device set-up (which shares the HIP runtime with the library)."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = str(tmp_path / "tuned.json")
+    print("gpu: tuner command line", flush=True)
+    r = subprocess.run([sys.executable, "-m", "paper_1809_03606_amd.tune", "--N", "128", "--K",
+                        "64", "--D", "8", "--frames", "2048", "--out", out],
+                       cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    entry = json.loads(r.stdout.strip().splitlines()[-1])
+    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in [
+        tuple(c) for c in __import__("paper_1809_03606_amd.tune", fromlist=["x"]).CANDIDATES]
+    assert json.load(open(out))
