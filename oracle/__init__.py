@@ -73,9 +73,18 @@ def lib():
                                                ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64,
                                                vp, vp, vp]
             L.orc_ml_decode.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int64]
+            L.orc_fssc_schedule.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
+            L.orc_node_candidates.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                              ctypes.c_double, vp, vp, ctypes.c_int]
+            L.orc_fsscs_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+            L.orc_fsscs_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                                 ctypes.c_int64, vp, vp, vp]
             for name in ("orc_construct", "orc_bhattacharyya_log", "orc_polar_transform",
                          "orc_encode_batch", "orc_sc_decode", "orc_scs_decode",
-                         "orc_scs_decode_batch", "orc_ml_decode"):
+                         "orc_scs_decode_batch", "orc_ml_decode", "orc_fssc_schedule",
+                         "orc_node_candidates", "orc_fsscs_decode", "orc_fsscs_decode_batch"):
                 getattr(L, name).restype = ctypes.c_int
             del u8p
             _lib = L
@@ -193,6 +202,80 @@ def scs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L:
         return L_.orc_scs_decode_batch(mode, N, _p(info), int(crc_bits), int(D), int(L),
                                        _p(a[lo:hi]), hi - lo, _p(pay[lo:hi]), _p(status[lo:hi]),
                                        _p(stats[lo:hi]))
+
+    threads = max(1, min(int(threads), B if B else 1))
+    if threads == 1:
+        _check(run(0, B))
+    else:
+        edges = np.linspace(0, B, threads + 1).astype(int)
+        with ThreadPoolExecutor(threads) as ex:
+            for rc in ex.map(lambda t: run(edges[t], edges[t + 1]), range(threads)):
+                _check(rc)
+    return pay, status, stats
+
+
+NODE_R0, NODE_R1, NODE_REP, NODE_SPC = 0, 1, 2, 3
+NODE_NAMES = ("R-0", "R-1", "REP", "SPC")
+TYPES_ALL = 0xF
+
+
+def fssc_schedule(info_mask: np.ndarray, types: int = TYPES_ALL):
+    """FSSC schedule (Section 3): list of (first leaf, lambda, class) in decoding order."""
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    N = int(info.size)
+    st, lam, ty = (np.zeros(N, np.int32) for _ in range(3))
+    cnt = lib().orc_fssc_schedule(N, _p(info), int(types), _p(st), _p(lam), _p(ty), N)
+    _check(min(cnt, 0))
+    return [(int(st[q]), int(lam[q]), int(ty[q])) for q in range(cnt)]
+
+
+def node_candidates(mode: int, node_type: int, alpha, pm: float = 0.0):
+    """FSSCL candidates of one node (Section 2.2.4): list of (estimates, metric)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    lam = int(a.size).bit_length() - 1
+    beta = np.zeros((16, a.size), np.uint8)
+    pms = np.zeros(16, np.float64)
+    cnt = lib().orc_node_candidates(mode, int(node_type), lam, _p(a), float(pm), _p(beta),
+                                    _p(pms), 16)
+    _check(min(cnt, 0))
+    return [(beta[q].copy(), float(pms[q])) for q in range(cnt)]
+
+
+def fsscs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
+                 types: int = TYPES_ALL):
+    """FSSCS-RM decoding of one frame (Section 4).  Returns (u_hat, status, pm, stats)."""
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    a = _llr_array(mode, llr)
+    u = np.zeros(info.size, np.uint8)
+    st = ctypes.c_uint8(0)
+    pm = ctypes.c_double(0.0)
+    s = _Stats()
+    _check(lib().orc_fsscs_decode(mode, int(info.size), _p(info), int(crc_bits), int(D), int(L),
+                                  int(types), _p(a), _p(u), ctypes.byref(st), ctypes.byref(pm),
+                                  ctypes.byref(s)))
+    return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
+
+
+def fsscs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
+                       threads: int = 1, types: int = TYPES_ALL):
+    """Decode frames llr[B][N] with FSSCS-RM; returns (payload[B][K-r], status[B], stats[B])."""
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    a = _llr_array(mode, llr)
+    N = int(info.size)
+    a = a.reshape(-1, N)
+    B = a.shape[0]
+    k = int(info.sum()) - int(crc_bits)
+    pay = np.zeros((B, k), np.uint8)
+    status = np.zeros(B, np.uint8)
+    stats = np.zeros(B, STATS_DTYPE)
+    L_ = lib()
+
+    def run(lo, hi):
+        if hi <= lo:
+            return 0
+        return L_.orc_fsscs_decode_batch(mode, N, _p(info), int(crc_bits), int(D), int(L),
+                                         int(types), _p(a[lo:hi]), hi - lo, _p(pay[lo:hi]),
+                                         _p(status[lo:hi]), _p(stats[lo:hi]))
 
     threads = max(1, min(int(threads), B if B else 1))
     if threads == 1:

@@ -424,6 +424,326 @@ int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const v
   return 0;
 }
 
+// ---------------------------------------------------------------------------------
+// Fast simplified decoding: FSSC nodes (Section 2.2.2), their FSSCL candidate rules
+// (Section 2.2.4), the FSSC schedule made once per code (Section 3, FSSC schedule
+// figure) and the stack decoder built on them, FSSCS-RM (Section 4).
+//
+// Readings:
+//  - node classes, tested in this order on the leaves of a node of Lambda = 2^lambda
+//    leaves: all frozen -> R-0; all information -> R-1; only the last leaf information
+//    (Lambda >= 2) -> REP; only the first leaf frozen (Lambda >= 4) -> SPC; otherwise the
+//    node is split into its two children.  A leaf is always R-0 or R-1.  `types` limits
+//    the classes used above the leaves (bit t = class t allowed).
+//  - candidates of a node, numbered in the order written in Section 2.2.4: R-0: one;
+//    REP: all-0 then all-1; R-1 (Chase-II on the two least reliable positions m1, m2):
+//    HD, flip m1, flip m2, flip both (a one-leaf R-1 node has only HD and flip m1); SPC
+//    (equations not given in the paper): the flip patterns of the four least reliable
+//    positions m1..m4 that make the node's parity even, taken in increasing order of the
+//    pattern read as a 4-bit number (bit k = flip m_(k+1)), which are 8 of the 16.
+//  - least reliable positions: ascending |alpha|, ties to the smaller index.
+//  - metrics: each flipped position adds its |alpha| to the path metric, in increasing
+//    k; R-0 and REP add the node sums of Section 2.2.4, summed pairwise with halving
+//    distance (w[j] += w[j + h] for h = Lambda/2, ..., 1), then one addition to PM.
+//  - a path stores its N-bit in-place beta array (Section 4): a node's estimates are
+//    written at [PL, PL + Lambda) and the beta operation XORs a completed right child
+//    into its left sibling in place, upwards while the parent is itself a right child.
+//    At PL = N the array holds the codeword estimate; u is its re-encoding (the
+//    transform is its own inverse), and the CRC and the payload are read from u.
+//  - an iteration is one node extension; the L counter is indexed by the node's first
+//    leaf, the path length before the extension; stack rules as for SCS.
+//  - the single alpha memory (Section 3.3) is valid for every child of the last
+//    extended path, whose beta arrays hold what the next node's g operations read; any
+//    other winner is a path switch and alpha is recomputed from the root.
+// ---------------------------------------------------------------------------------
+enum { NODE_R0 = 0, NODE_R1 = 1, NODE_REP = 2, NODE_SPC = 3 };
+
+struct FNode {
+  int start, lam, type;
+};
+
+void fssc_nodes(int lam, int phi, const uint8_t* info, int types, std::vector<FNode>& out) {
+  const int Lam = 1 << lam, start = phi * Lam;
+  int k = 0;
+  for (int j = 0; j < Lam; ++j) k += info[start + j] ? 1 : 0;
+  int type = -1;
+  if (lam == 0) {
+    type = k ? NODE_R1 : NODE_R0;
+  } else if (k == 0 && (types & (1 << NODE_R0))) {
+    type = NODE_R0;
+  } else if (k == Lam && (types & (1 << NODE_R1))) {
+    type = NODE_R1;
+  } else if (k == 1 && info[start + Lam - 1] && (types & (1 << NODE_REP))) {
+    type = NODE_REP;
+  } else if (Lam >= 4 && k == Lam - 1 && !info[start] && (types & (1 << NODE_SPC))) {
+    type = NODE_SPC;
+  }
+  if (type >= 0) {
+    out.push_back(FNode{start, lam, type});
+    return;
+  }
+  fssc_nodes(lam - 1, 2 * phi, info, types, out);
+  fssc_nodes(lam - 1, 2 * phi + 1, info, types, out);
+}
+
+// Sum with halving distance: w[j] += w[j + h], h = Lambda/2, ..., 1.
+template <class A>
+typename A::PM node_sum(std::vector<typename A::PM> w) {
+  for (size_t h = w.size() / 2; h >= 1; h /= 2)
+    for (size_t j = 0; j < h; ++j) w[j] = w[j] + w[j + h];
+  return w[0];
+}
+
+// Least reliable positions of alpha_v: the first `cnt` indices in ascending |alpha|,
+// ties to the smaller index.
+template <class A>
+std::vector<int> least_reliable(const std::vector<typename A::T>& a, int cnt) {
+  std::vector<int> idx(a.size());
+  for (size_t j = 0; j < a.size(); ++j) idx[j] = (int)j;
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int x, int y) { return A::mag(a[x]) < A::mag(a[y]); });
+  idx.resize((size_t)cnt);
+  return idx;
+}
+
+template <class A>
+struct Cand {
+  std::vector<uint8_t> beta;
+  typename A::PM pm;
+};
+
+// FSSCL candidate rules (Section 2.2.4) for one node.
+template <class A>
+std::vector<Cand<A>> node_candidates(int type, const std::vector<typename A::T>& a,
+                                     typename A::PM pm) {
+  typedef typename A::PM PM;
+  const int Lam = (int)a.size();
+  std::vector<uint8_t> hd(Lam);
+  for (int j = 0; j < Lam; ++j) hd[j] = (uint8_t)A::hd(a[j]);
+  std::vector<Cand<A>> out;
+  if (type == NODE_R0 || type == NODE_REP) {
+    std::vector<PM> w0(Lam), w1(Lam);
+    for (int j = 0; j < Lam; ++j) {
+      w0[j] = hd[j] ? A::mag(a[j]) : PM(0);   // HD(alpha) |alpha|
+      w1[j] = hd[j] ? PM(0) : A::mag(a[j]);   // (1 - HD(alpha)) |alpha|
+    }
+    out.push_back(Cand<A>{std::vector<uint8_t>(Lam, 0), A::pm_add(pm, node_sum<A>(w0))});
+    if (type == NODE_REP)
+      out.push_back(Cand<A>{std::vector<uint8_t>(Lam, 1), A::pm_add(pm, node_sum<A>(w1))});
+    return out;
+  }
+  const int nlr = type == NODE_R1 ? (Lam >= 2 ? 2 : 1) : 4;
+  const std::vector<int> m = least_reliable<A>(a, nlr);
+  int parity = 0;
+  for (int j = 0; j < Lam; ++j) parity ^= hd[j];
+  for (int mask = 0; mask < (1 << nlr); ++mask) {
+    if (type == NODE_SPC && (__builtin_popcount((unsigned)mask) & 1) != parity) continue;
+    Cand<A> c{hd, pm};
+    for (int k = 0; k < nlr; ++k)
+      if (mask & (1 << k)) {
+        c.beta[m[k]] ^= 1;
+        c.pm = A::pm_add(c.pm, A::mag(a[m[k]]));
+      }
+    out.push_back(c);
+  }
+  return out;
+}
+
+// Alpha memory of Section 3.1 for the fast schedule: the g operations read the left
+// sibling's estimates from the path's in-place beta array.
+template <class A>
+struct FTree {
+  typedef typename A::T T;
+  int n = 0;
+  std::vector<std::vector<T>> alpha;
+  uint64_t f_ops = 0, g_ops = 0;
+
+  void init(int n_, const void* llr) {
+    n = n_;
+    alpha.assign(n + 1, std::vector<T>());
+    for (int lam = 0; lam <= n; ++lam) alpha[lam].assign(1u << lam, T(0));
+    for (int j = 0; j < (1 << n); ++j) alpha[n][j] = load_llr<A>(llr, j);
+  }
+
+  // eq. (llrcalc) for node (lambda, phi); beta: the path's N-bit array.
+  void node_alpha(int lam, int phi, const uint8_t* beta) {
+    const int Lam = 1 << lam;
+    const T* ap = alpha[lam + 1].data();
+    T* av = alpha[lam].data();
+    if ((phi & 1) == 0) {
+      for (int i = 0; i < Lam; ++i) av[i] = A::f(ap[i], ap[i + Lam]);
+      f_ops += Lam;
+    } else {
+      const uint8_t* bu = beta + (size_t)(phi - 1) * Lam;  // left sibling, in place
+      for (int i = 0; i < Lam; ++i) av[i] = A::g(ap[i], ap[i + Lam], bu[i]);
+      g_ops += Lam;
+    }
+  }
+
+  // Algorithm 1 from node (lambda, phi); with `switched`, Algorithm 4 (from the root).
+  void calc_alpha(int lam, int phi, bool switched, const uint8_t* beta) {
+    if (lam == n) return;
+    if ((phi & 1) == 0 || switched) calc_alpha(lam + 1, phi >> 1, switched, beta);
+    node_alpha(lam, phi, beta);
+  }
+};
+
+// The beta operation in place (Section 4): a completed right child is XORed into its left
+// sibling, which turns the pair into the parent's estimates; repeat upwards.
+void beta_in_place(uint8_t* beta, int n, int lam, int phi) {
+  while (lam < n && (phi & 1)) {
+    const int Lam = 1 << lam;
+    uint8_t* left = beta + (size_t)(phi - 1) * Lam;
+    const uint8_t* right = beta + (size_t)phi * Lam;
+    for (int i = 0; i < Lam; ++i) left[i] ^= right[i];
+    ++lam;
+    phi >>= 1;
+  }
+}
+
+template <class A>
+struct FPath {
+  typename A::PM pm;
+  int pl;
+  uint32_t seq;
+  std::vector<uint8_t> beta;  // N bits, in place
+};
+
+template <class A>
+bool fkey_less(const FPath<A>& a, const FPath<A>& b) {
+  if (a.pm < b.pm) return true;
+  if (b.pm < a.pm) return false;
+  if (a.pl != b.pl) return a.pl > b.pl;
+  return a.seq < b.seq;
+}
+
+template <class A>
+int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int types,
+                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                   orc_stats* st) {
+  const int N = 1 << n;
+  std::vector<FNode> sched;
+  fssc_nodes(n, 0, info, types, sched);
+  std::vector<int> node_at(N, -1);  // the schedule position of a path of length PL
+  for (size_t q = 0; q < sched.size(); ++q) node_at[sched[q].start] = (int)q;
+
+  FTree<A> t;
+  t.init(n, llr);
+  orc_stats s;
+  std::memset(&s, 0, sizeof s);
+  std::vector<FPath<A>> S;
+  S.push_back(FPath<A>{typename A::PM(0), 0, 0u, std::vector<uint8_t>(N, 0)});
+  uint32_t next_seq = 1;
+  std::vector<int> count(N, 0);
+  int fails = 0;
+  bool have_fallback = false;
+  FPath<A> fallback, result;
+  const FPath<A>* out = nullptr;
+  uint8_t stat = 0;
+  // children of the last extension (the paths the alpha memory is valid for)
+  bool mem_valid = false;
+  uint32_t mem_lo = 0, mem_hi = 0;
+  int mem_pl = -1;
+
+  for (;;) {
+    if (S.empty()) {
+      stat = ORC_ST_FALLBACK | ORC_ST_EXHAUSTED;
+      out = have_fallback ? &fallback : nullptr;
+      break;
+    }
+    size_t w = 0;
+    for (size_t q = 1; q < S.size(); ++q)
+      if (fkey_less<A>(S[q], S[w])) w = q;
+    FPath<A> p = S[w];
+    S.erase(S.begin() + (long)w);
+
+    if (p.pl == N) {
+      ++s.completions;
+      std::vector<uint8_t> u(N);
+      orc_polar_transform(N, p.beta.data(), u.data());  // re-encode the codeword estimate
+      if (crc_passes(N, info, crc_bits, u.data())) {
+        result = p;
+        out = &result;
+        stat = ORC_ST_OK;
+        break;
+      }
+      if (!have_fallback) {
+        fallback = p;
+        have_fallback = true;
+      }
+      if (++fails >= L) {
+        stat = ORC_ST_FALLBACK;
+        out = &fallback;
+        break;
+      }
+      continue;
+    }
+
+    const int i = p.pl;
+    const FNode& v = sched[(size_t)node_at[i]];
+    const int Lam = 1 << v.lam, phi = i >> v.lam;
+    ++s.iterations;
+    s.sc_elems += (i == 0) ? (uint64_t)(N - Lam)
+                           : ((2ull << __builtin_ctz((unsigned)i)) - (uint64_t)Lam);
+
+    const bool cont = mem_valid && p.pl == mem_pl && p.seq >= mem_lo && p.seq <= mem_hi;
+    if (!cont) ++s.switches;
+    t.calc_alpha(v.lam, phi, !cont, p.beta.data());
+    const std::vector<typename A::T> a(t.alpha[v.lam].begin(), t.alpha[v.lam].end());
+
+    std::vector<FPath<A>> kids;
+    for (const Cand<A>& c : node_candidates<A>(v.type, a, p.pm)) {
+      FPath<A> k = p;
+      k.pl = i + Lam;
+      k.pm = c.pm;
+      k.seq = next_seq++;
+      std::copy(c.beta.begin(), c.beta.end(), k.beta.begin() + i);
+      beta_in_place(k.beta.data(), n, v.lam, phi);
+      kids.push_back(k);
+    }
+    mem_valid = true;
+    mem_lo = kids.front().seq;
+    mem_hi = kids.back().seq;
+    mem_pl = i + Lam;
+
+    for (auto& c : kids) {
+      if ((int)S.size() < D) {
+        S.push_back(c);
+        continue;
+      }
+      size_t wq = 0;
+      for (size_t q = 1; q < S.size(); ++q)
+        if (fkey_less<A>(S[wq], S[q])) wq = q;
+      if (fkey_less<A>(c, S[wq])) {
+        S[wq] = c;
+        ++s.evictions;
+      } else {
+        ++s.drops;
+      }
+    }
+    if (++count[i] == L) {
+      ++s.prunes;
+      std::vector<FPath<A>> keep;
+      for (auto& q : S)
+        if (q.pl > i) keep.push_back(q);
+      S.swap(keep);
+    }
+  }
+
+  s.f_ops = t.f_ops;
+  s.g_ops = t.g_ops;
+  if (out) {
+    orc_polar_transform(N, out->beta.data(), u_hat);
+    if (pm_out) *pm_out = (double)out->pm;
+  } else {
+    std::memset(u_hat, 0, (size_t)N);
+    if (pm_out) *pm_out = 0.0;
+  }
+  *status = stat;
+  if (st) *st = s;
+  return 0;
+}
+
 // Bhattacharyya parameters in the log domain (R17): z0 = exp(-R * Eb/N0) for BPSK on
 // AWGN; the "minus" (f) child of z is 2z - z^2 and the "plus" (g) child is z^2.
 // Indices: the children of index j are 2j (minus) and 2j+1 (plus), so the first split
@@ -598,6 +918,83 @@ int orc_ml_decode(int N, const uint8_t* info_mask, const double* llr, double* di
   }
   *disc_min = best;
   *n_min = cnt;
+  return 0;
+}
+
+int orc_fssc_schedule(int N, const uint8_t* info_mask, int types, int32_t* start, int32_t* lam,
+                      int32_t* type, int max_nodes) {
+  const int n = log2_exact(N);
+  if (n < 0) return -1;
+  std::vector<FNode> sched;
+  fssc_nodes(n, 0, info_mask, types, sched);
+  for (size_t q = 0; q < sched.size() && (int)q < max_nodes; ++q) {
+    start[q] = sched[q].start;
+    lam[q] = sched[q].lam;
+    type[q] = sched[q].type;
+  }
+  return (int)sched.size();
+}
+
+int orc_node_candidates(int mode, int type, int lam, const double* alpha, double pm,
+                        uint8_t* beta_out, double* pm_out, int max_out) {
+  const int Lam = 1 << lam;
+  if (type < 0 || type > 3 || lam < 0 || lam > 11) return -1;
+  if ((type == NODE_SPC && Lam < 4) || (type == NODE_REP && Lam < 2)) return -1;
+  int cnt = 0;
+  auto emit = [&](const std::vector<uint8_t>& b, double m) {
+    if (cnt < max_out) {
+      std::memcpy(beta_out + (size_t)cnt * Lam, b.data(), (size_t)Lam);
+      pm_out[cnt] = m;
+    }
+    ++cnt;
+  };
+  if (mode == ORC_F64) {
+    std::vector<double> a(alpha, alpha + Lam);
+    for (auto& c : node_candidates<ArF64>(type, a, pm)) emit(c.beta, c.pm);
+  } else if (mode == ORC_F32) {
+    std::vector<float> a(Lam);
+    for (int j = 0; j < Lam; ++j) a[j] = (float)alpha[j];
+    for (auto& c : node_candidates<ArF32>(type, a, (float)pm)) emit(c.beta, (double)c.pm);
+  } else {
+    std::vector<int> a(Lam);
+    for (int j = 0; j < Lam; ++j) a[j] = (int)alpha[j];
+    for (auto& c : node_candidates<ArFix>(type, a, (int)pm)) emit(c.beta, (double)c.pm);
+  }
+  return cnt;
+}
+
+int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                     int types, const void* llr, uint8_t* u_hat, uint8_t* status,
+                     double* pm_out, orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  switch (mode) {
+    case ORC_F32: return fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
+    case ORC_F64: return fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
+    case ORC_FIX: return fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
+  }
+  return -1;
+}
+
+int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
+                           int L, int types, const void* llr, int64_t B, uint8_t* payload,
+                           uint8_t* status, orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0) return -1;
+  const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
+  int K = 0;
+  for (int j = 0; j < N; ++j) K += info_mask[j] ? 1 : 0;
+  const int k = K - crc_bits;
+  std::vector<uint8_t> u(N);
+  for (int64_t b = 0; b < B; ++b) {
+    int rc = orc_fsscs_decode(mode, N, info_mask, crc_bits, D, L, types,
+                              (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
+                              nullptr, st ? st + b : nullptr);
+    if (rc) return rc;
+    int q = 0;
+    for (int j = 0; j < N && q < k; ++j)
+      if (info_mask[j]) payload[b * k + q++] = u[j];
+  }
   return 0;
 }
 

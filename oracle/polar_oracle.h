@@ -1,6 +1,6 @@
 /*
  * polar_oracle.h -- plain CPU reference ("oracle") for polar-code construction,
- * encoding, SC and SCS decoding.
+ * encoding, SC, SCS and fast simplified stack (FSSCS-RM) decoding.
  *
  * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP decoder.  Only the
  * test suite, the smoke check and the benchmark's CPU-baseline leg may load it; the
@@ -82,6 +82,30 @@ int orc_scs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int 
 int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
                          int L, const void* llr, int64_t B, uint8_t* payload,
                          uint8_t* status, orc_stats* st);
+
+/* Fast simplified decoding (Sections 2.2.2, 2.2.4, 3 and 4).  Node classes: */
+enum { ORC_NODE_R0 = 0, ORC_NODE_R1 = 1, ORC_NODE_REP = 2, ORC_NODE_SPC = 3 };
+/* `types`: bit t allows class t above the leaves (0xF: all; 0: leaves only). */
+#define ORC_TYPES_ALL 0xF
+
+/* FSSC schedule: the nodes in decoding order (first leaf, lambda, class), at most
+ * max_nodes written; returns the number of nodes. */
+int orc_fssc_schedule(int N, const uint8_t* info_mask, int types, int32_t* start, int32_t* lam,
+                      int32_t* type, int max_nodes);
+
+/* FSSCL candidates of one node (class, lambda) with node LLRs alpha[2^lambda] (converted
+ * to the mode's type) and path metric pm: writes each candidate's 2^lambda estimates and
+ * its metric, in creation order; returns the number of candidates. */
+int orc_node_candidates(int mode, int type, int lam, const double* alpha, double pm,
+                        uint8_t* beta_out, double* pm_out, int max_out);
+
+/* FSSCS-RM decoding of one frame (stack rules as orc_scs_decode, one iteration per node). */
+int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                     int types, const void* llr, uint8_t* u_hat, uint8_t* status,
+                     double* pm_out, orc_stats* st);
+int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
+                           int L, int types, const void* llr, int64_t B, uint8_t* payload,
+                           uint8_t* status, orc_stats* st);
 
 /* Brute-force ML over all 2^K information words (K <= 20): discrepancy
  * disc(c) = sum_{j: c_j != HD(llr_j)} |llr_j| in binary64.  Returns the minimum in
