@@ -176,6 +176,31 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
 int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8_t* payload_dev,
                      uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream);
 
+/* The fast simplified schedule of a code (Sections 2.2.2 and 3): nodes_out[N] receives,
+ * for the first leaf i of every node, (class << 4) | lambda (the node covers leaves
+ * [i, i + 2^lambda); classes 0 R-0, 1 R-1, 2 REP, 3 SPC) and 0xFF at every other position.
+ * A block of leaves is one node when all its leaves are frozen (R-0), all carry information
+ * (R-1), only its last leaf carries information (REP, 2 or more leaves) or only its first
+ * leaf is frozen (SPC, 4 or more leaves); any other block is split in halves.
+ * Errors: POLAR_EINVAL for NULL arguments. */
+int polar_code_schedule(const polar_code* code, uint8_t* nodes_out);
+
+/* Fast simplified stack decoding, FSSCS-RM (Section 4): the SCS search of scs_decode_batch
+ * where one extension decodes a whole node of the schedule above and puts every candidate
+ * of the node's list rule (Section 2.2.4) on the stack: R-0 one (all 0); REP two (all 0,
+ * all 1); R-1 four (hard decisions, and flips of the one or two least reliable positions;
+ * two for a single leaf); SPC eight (the flip patterns of the four least reliable positions
+ * that give even parity).  A candidate's metric adds |alpha| of every position where it
+ * differs from the hard decision.  Stack depth D, L counter (indexed by the node's first
+ * leaf), CRC check, outputs, status bits and statistics as scs_decode_batch (iterations =
+ * node extensions; a path switch = a winner that is not a candidate of the last
+ * extension).  Errors: as scs_decode_batch; POLAR_EUNSUPPORTED when L times the candidates
+ * of one pass over the schedule exceeds 2^20 - 2. */
+int fsscs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
+                       int32_t llr_dtype, const void* llr_dev, int64_t n_frames,
+                       uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
+                       void* hip_stream);
+
 /* Last HIP error seen by a call on this context (POLAR_OK if none), then cleared. */
 int scs_ctx_last_error(scs_ctx* ctx);
 

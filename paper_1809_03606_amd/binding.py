@@ -25,7 +25,8 @@ SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
-           "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror")
+           "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
+           "polar_code_schedule", "fsscs_decode_batch")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
                 "drops", "prunes")
@@ -88,12 +89,15 @@ def lib():
             L.scs_ctx_last_error.argtypes = [vp]
             L.scs_ctx_set_lanes.argtypes = [vp, i32]
             L.scs_ctx_set_waves_per_block.argtypes = [vp, i32]
+            L.polar_code_schedule.argtypes = [vp, vp]
+            L.fsscs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
-                      "scs_ctx_set_waves_per_block", "scs_ctx_last_error"):
+                      "scs_ctx_set_waves_per_block", "scs_ctx_last_error",
+                      "polar_code_schedule", "fsscs_decode_batch"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -179,6 +183,21 @@ def scs_decode_batch(ctx: int, code: int, D: int, L: int, llr_dtype: int, llr_de
     _check(lib().scs_decode_batch(ctx, code, int(D), int(L), int(llr_dtype), _addr(llr_dev),
                                   int(n_frames), _addr(payload_dev), _addr(status_dev),
                                   _addr(stats_dev), _stream(stream)), "scs_decode_batch")
+
+
+def fsscs_decode_batch(ctx: int, code: int, D: int, L: int, llr_dtype: int, llr_dev, n_frames: int,
+                       payload_dev, status_dev, stats_dev=None, stream=None):
+    _check(lib().fsscs_decode_batch(ctx, code, int(D), int(L), int(llr_dtype), _addr(llr_dev),
+                                    int(n_frames), _addr(payload_dev), _addr(status_dev),
+                                    _addr(stats_dev), _stream(stream)), "fsscs_decode_batch")
+
+
+def polar_code_schedule(handle: int) -> list:
+    """The code's fast simplified schedule: [(first leaf, lambda, class)] in order."""
+    N, _, _, _ = polar_code_query(handle)
+    raw = np.zeros(N, np.uint8)
+    _check(lib().polar_code_schedule(handle, raw.ctypes.data), "polar_code_schedule")
+    return [(int(j), int(v) & 15, int(v) >> 4) for j, v in enumerate(raw) if v != 0xFF]
 
 
 def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_dev, payload_dev,
@@ -272,15 +291,17 @@ class ScsContext:
         scs_ctx_set_waves_per_block(self.handle, waves_per_block)
 
     def decode(self, code: PolarCode, D: int, L: int, llr_dev, payload_dev, status_dev,
-               stats_dev=None, stream=None):
+               stats_dev=None, stream=None, fast: bool = False):
+        """SCS decoding of llr_dev (frames x N); fast=True: FSSCS-RM (fsscs_decode_batch)."""
         import torch  # device buffers are torch tensors here
 
         dtype = SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8
         if llr_dev.dtype not in (torch.float32, torch.int8):
             raise TypeError("LLRs must be float32 or int8")
         n = llr_dev.numel() // code.N
-        scs_decode_batch(self.handle, code.handle, D, L, dtype, llr_dev, n, payload_dev,
-                         status_dev, stats_dev, stream)
+        fn = fsscs_decode_batch if fast else scs_decode_batch
+        fn(self.handle, code.handle, D, L, dtype, llr_dev, n, payload_dev, status_dev, stats_dev,
+           stream)
 
     def close(self):
         if self.handle:

@@ -1,0 +1,651 @@
+// Fast simplified stack decoding (FSSCS-RM) of polar codes on gfx950.
+//
+// Method: Aurora & Gross, Section 4: the SCS search of Section 2.2.5 where one extension
+// decodes a whole fast-decoding node (R-0, REP, R-1, SPC; Section 2.2.2) and places every
+// candidate of the node's list rule (Section 2.2.4) on the stack, with one alpha tree per
+// frame recomputed on a path switch (the reduced-memory scheme of Section 3.3).
+//
+// Mapping: as the SCS kernel (one wavefront per frame, stack slot s = lane s holding a
+// 64-bit key, the decided bits u of slot s in lane-private memory, L counters and the
+// alpha tree in LDS).  Per extension:
+//   * the alpha tree is computed from the first stale stage down to the node's stage
+//     lambda (not to the leaves);
+//   * the node's 2^lambda LLRs sit one per lane (up to 64) or in LDS, 64 per row;
+//   * the candidates follow the rules of Section 2.2.4, with these readings: least reliable
+//     positions in ascending |alpha|, ties to the smaller index; SPC keeps the flip patterns
+//     of its four least reliable positions that give even parity, in increasing order of
+//     the pattern as a 4-bit number; R-0 and REP metrics add the node sum taken pairwise
+//     with halving distance (w[j] += w[j + h], h = 2^lambda / 2, ..., 1);
+//   * a candidate's bits are kept in the u domain: u = (hard decisions) re-encoded, and a
+//     flip at position m adds the indicator of the subsets of m (the row m of the
+//     transform), because the transform is linear and its own inverse.
+#include <hip/hip_runtime.h>
+
+#include "polarscs.h"
+#include "scs_device.h"
+#include "scs_launch.h"
+#include "scs_tree.h"
+
+namespace {
+
+constexpr int kNodeR0 = 0, kNodeR1 = 1, kNodeRep = 2, kNodeSpc = 3;
+
+// Plain sum of two non-negative metric terms (the node sums; no saturation inside a sum).
+__device__ __forceinline__ uint32_t term_add(TrF32, uint32_t a, uint32_t b) {
+  return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+}
+__device__ __forceinline__ uint32_t term_add(TrI8, uint32_t a, uint32_t b) { return a + b; }
+
+// Stages top .. bottom (both >= 6) of the tree for leaf position i, 64 values per
+// instruction, as in the SCS kernel's big stages.
+template <int LAM, int LOGN, class TR, bool STATS>
+__device__ __forceinline__ void big_stages_to(int top, int bottom, int i, uint32_t u,
+                                              const typename TR::In* __restrict__ root,
+                                              uint32_t* al, int lane, uint32_t& fg) {
+  if constexpr (LAM >= 6) {
+    if (LAM <= top && LAM >= bottom) {
+      constexpr int Lam = 1 << LAM;
+      const bool odd = (i >> LAM) & 1;
+      const int base = ((i >> LAM) - 1) << LAM;
+      uint32_t bx = 0u;
+      if (odd) bx = sibling_big<LAM>(u, base, lane);
+      uint32_t* dst = al + (Lam - 1);
+      const uint32_t* src = al + (2 * Lam - 1);
+      if (!odd) {
+#pragma unroll
+        for (int r = 0; r < Lam / kWave; ++r) {
+          const int e = r * kWave + lane;
+          if constexpr (LAM + 1 == LOGN)
+            dst[e] = TR::f(TR::load(root, e), TR::load(root, e + Lam));
+          else
+            dst[e] = TR::f(src[e], src[e + Lam]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < Lam / kWave; ++r) {
+          const int e = r * kWave + lane;
+          const int w0 = (base >> 5) + 2 * r;
+          const uint32_t mlo = readlane(bx, w0), mhi = readlane(bx, w0 + 1);
+          const uint32_t m = lane < 32 ? mlo : mhi;
+          const bool ub = (m >> (lane & 31)) & 1u;
+          if constexpr (LAM + 1 == LOGN)
+            dst[e] = TR::g(TR::load(root, e), TR::load(root, e + Lam), ub);
+          else
+            dst[e] = TR::g(src[e], src[e + Lam], ub);
+        }
+      }
+      if constexpr (STATS) fg += (uint32_t)Lam;
+      lds_order();
+    }
+    big_stages_to<LAM - 1, LOGN, TR, STATS>(top, bottom, i, u, root, al, lane, fg);
+  }
+}
+
+// Register stages LAM .. stop (LAM <= start), each stored for later nodes.
+template <int LAM, class TR, bool STATS>
+__device__ __forceinline__ void small_chain_to(uint32_t& x, int start, int stop, int i,
+                                               uint32_t u, uint32_t* al, uint32_t* dummy,
+                                               int lane, uint32_t& fg) {
+  if constexpr (LAM >= 0) {
+    if (LAM <= start && LAM >= stop) {
+      x = reg_stage<LAM, TR>(x, i, u, lane);
+      if constexpr (LAM >= 1)
+        *(lane < (1 << LAM) ? &al[(1 << LAM) - 1 + lane] : &dummy[lane]) = x;
+      if constexpr (STATS) fg += 1u << LAM;
+    }
+    small_chain_to<LAM - 1, TR, STATS>(x, start, stop, i, u, al, dummy, lane, fg);
+  }
+}
+
+// Alpha of node (lam, i >> lam) below the root: stages top .. lam (top >= lam).  For
+// lam <= 5 the values come back one per lane (lane e = value e); for lam >= 6 they are
+// left in LDS at al[2^lam - 1 + e].
+template <int LOGN, class TR, bool STATS>
+__device__ __forceinline__ uint32_t node_alpha(int top, int lam, int i, uint32_t u,
+                                               const typename TR::In* __restrict__ root,
+                                               uint32_t* al, uint32_t* dummy, int lane,
+                                               uint32_t& fg) {
+  constexpr int SM = Layout<LOGN>::SMALL;
+  if (top >= 6)
+    big_stages_to<LOGN - 1, LOGN, TR, STATS>(top, lam > 6 ? lam : 6, i, u, root, al, lane, fg);
+  if (lam >= 6) return 0u;
+  const int start = top < SM ? top : SM;
+  const int nin = 2 << start;
+  const int q = lane < nin ? lane : nin - 1;
+  uint32_t x;
+  if (start + 1 == LOGN)
+    x = TR::load(root, q);
+  else
+    x = al[nin - 1 + q];
+  small_chain_to<SM, TR, STATS>(x, start, lam, i, u, al, dummy, lane, fg);
+  lds_order();
+  return x;
+}
+
+// Lane-wise sum with halving distance over lanes < n (n a power of two <= 64); lane 0
+// holds the result.
+template <class TR>
+__device__ __forceinline__ uint32_t lane_halving_sum(uint32_t w, int n) {
+  for (int h = n >> 1; h >= 1; h >>= 1) w = term_add(TR(), w, xor_lane_rt(w, h));
+  return readlane(w, 0);
+}
+
+// Node sums of Section 2.2.4: s0 = sum of HD(alpha)|alpha|, s1 = sum of (1 - HD(alpha))|alpha|,
+// each taken pairwise with halving distance.  Up to 64 values: one per lane in x.  More:
+// the values are in LDS (`vals`, n words); the first step writes the s0 terms to
+// vals[0, n/2) and the s1 terms to vals[n/2, n) (each lane reads both of its inputs before
+// writing them), then each half halves in place.
+template <class TR>
+__device__ __forceinline__ void node_sums(int lam, uint32_t x, uint32_t* vals, int lane,
+                                          uint32_t& s0, uint32_t& s1) {
+  const int n = 1 << lam;
+  auto t0 = [](uint32_t a) -> uint32_t { return TR::hd(a) ? TR::mag(a) : 0u; };
+  auto t1 = [](uint32_t a) -> uint32_t { return TR::hd(a) ? 0u : TR::mag(a); };
+  if (n <= kWave) {
+    s0 = lane_halving_sum<TR>(lane < n ? t0(x) : 0u, n);
+    s1 = lane_halving_sum<TR>(lane < n ? t1(x) : 0u, n);
+    return;
+  }
+  const int h0 = n / 2;
+  for (int j = lane; j < h0; j += kWave) {
+    const uint32_t a = vals[j], b = vals[j + h0];
+    vals[j] = term_add(TR(), t0(a), t0(b));
+    vals[j + h0] = term_add(TR(), t1(a), t1(b));
+  }
+  lds_order();
+  for (int h = h0 / 2; h >= kWave; h >>= 1) {
+    for (int j = lane; j < h; j += kWave) {
+      vals[j] = term_add(TR(), vals[j], vals[j + h]);
+      vals[h0 + j] = term_add(TR(), vals[h0 + j], vals[h0 + j + h]);
+    }
+    lds_order();
+  }
+  s0 = lane_halving_sum<TR>(vals[lane], kWave);
+  s1 = lane_halving_sum<TR>(vals[h0 + lane], kWave);
+}
+
+// Position of the smallest |alpha| among the node's values, skipping positions in
+// `skip[0..nskip)`; ties go to the smaller position.
+__device__ __forceinline__ int node_argmin(int lam, const uint32_t* mag_reg, const uint32_t* vals,
+                                           const int* skip, int nskip, int lane, bool i8) {
+  (void)i8;
+  const int n = 1 << lam;
+  uint32_t best = 0xFFFFFFFFu;
+  int bidx = 0x7FFFFFFF;
+  if (n <= kWave) {
+    if (lane < n) {
+      bool sk = false;
+      for (int k = 0; k < nskip; ++k) sk |= skip[k] == lane;
+      if (!sk) {
+        best = *mag_reg;
+        bidx = lane;
+      }
+    }
+  } else {
+    for (int e = lane; e < n; e += kWave) {
+      bool sk = false;
+      for (int k = 0; k < nskip; ++k) sk |= skip[k] == e;
+      const uint32_t m = vals[e];
+      if (!sk && m < best) {
+        best = m;
+        bidx = e;
+      }
+    }
+  }
+  const uint32_t mb = wave_min(best);
+  const uint32_t key = best == mb ? (uint32_t)bidx : 0xFFFFFFFFu;
+  return (int)wave_min(key);
+}
+
+// Indicator of the subsets of m within a 32-bit word (row m & 31 of the transform).
+__device__ __forceinline__ uint32_t subsets32(int m) {
+  uint32_t x = 1u << (m & 31);
+#pragma unroll
+  for (int s = 0; s < 5; ++s) x ^= (x >> (1 << s)) & kLowMask[s];
+  return x;
+}
+
+struct NodeBlock {
+  // The node's bits in the u domain as lane-per-word values: lane w holds word w of the
+  // frame's bit vector for the words the node covers (`in` marks them); a node of fewer
+  // than 32 leaves is a bit field of one word, merged with the path's other bits there.
+  uint32_t word;
+  bool in;
+};
+
+template <int LOGN, class TR, bool STATS>
+__device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob& job,
+                                            uint32_t* lds) {
+  using LY = Layout<LOGN>;
+  constexpr int N = LY::N;
+  constexpr int W = LY::W;
+  const int lane = lane_id();
+  const int D = job.D, L = job.L;
+  const bool use_crc = code.crc != 0;
+  const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
+  uint32_t prow[kMaxD + 1];
+  uint32_t* cnt32 = lds;
+  uint32_t* al = cnt32 + (N + 3) / 4;
+  uint32_t* dummy = al + N;
+
+  const uint32_t infow = lane < W ? code.info[lane] : 0u;
+  for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
+  lds_order();
+
+  uint64_t s_key = make_key(0u, key_lo(N, 0, 0u));
+  uint64_t vmask = 1ull;
+  const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
+  uint32_t next_seq = 1;
+  uint64_t cand = kNone, lb = 0ull;
+  int cand_slot = 0;
+  uint64_t maxk = kNone;
+  int max_slot = 0;
+  // the tree: position of the node it was last computed for, that node's stage, and the
+  // bits of the path it follows; children of that extension: sequence numbers [c_lo, c_hi)
+  int wl = -1, wlam = 0;
+  uint32_t ucur = 0u;
+  uint32_t c_lo = 0u, c_hi = 0u;
+
+  uint32_t fb = 0u, out = 0u;
+  bool have_fb = false;
+  int fails = 0;
+  uint32_t st = 0u;
+  uint32_t n_it = 0, n_sw = 0, n_cp = 0, n_sc = 0, n_fg = 0, n_ev = 0, n_dr = 0, n_pr = 0;
+
+  uint32_t budget = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
+  for (;;) {
+    if (budget == 0u) {
+      st = 0u;
+      break;
+    }
+    --budget;
+    int p;
+    uint64_t pk;
+    bool cont;
+    if (cand < lb) {
+      p = cand_slot;
+      pk = cand;
+      cont = true;
+    } else {
+      if (vmask == 0ull) {
+        st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
+        out = fb;
+        break;
+      }
+      const bool live = (vmask >> lane) & 1ull;
+      const uint32_t kh = live ? (uint32_t)(s_key >> 32) : 0xFFFFFFFFu;
+      const uint32_t mh = wave_min(kh);
+      const uint64_t tie = ballot(kh == mh) & vmask;
+      uint32_t ml;
+      if (__builtin_popcountll(tie) == 1) {
+        p = __builtin_ctzll(tie);
+        ml = readlane((uint32_t)s_key, p);
+        lb = (uint64_t)wave_min(lane != p ? kh : 0xFFFFFFFFu) << 32;
+      } else {
+        const uint32_t kl = ((tie >> lane) & 1ull) ? (uint32_t)s_key : 0xFFFFFFFFu;
+        ml = wave_min(kl);
+        p = __builtin_ctzll(ballot(kl == ml) & tie);
+        lb = make_key(mh, ml + 1u);
+      }
+      pk = make_key(mh, ml);
+      cont = pk == cand;
+    }
+    vmask &= ~(1ull << p);
+    if (max_slot == p) maxk = kNone;
+    cand = kNone;
+    const uint32_t plo = (uint32_t)pk;
+    const int i = N - (int)(plo >> kSeqBits);
+
+    if (i == N) {
+      if constexpr (STATS) ++n_cp;
+      const uint32_t row = lane < W ? prow[p] : 0u;
+      if (!use_crc || crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
+        st = SCS_STATUS_OK;
+        out = row;
+        break;
+      }
+      if (!have_fb) {
+        fb = row;
+        have_fb = true;
+      }
+      if (++fails >= L) {
+        st = SCS_STATUS_FALLBACK;
+        out = fb;
+        break;
+      }
+      continue;
+    }
+
+    // ---- the node at position i ---------------------------------------------------
+    const uint32_t nd = code.nodes[i];
+    const int lam = (int)(nd & 15u), cls = (int)(nd >> 4);
+    const int Lam = 1 << lam;
+    if constexpr (STATS) {
+      ++n_it;
+      const uint32_t seq = plo & kSeqMask;
+      if (!(seq >= c_lo && seq < c_hi)) ++n_sw;
+      n_sc += (i == 0) ? (uint32_t)(N - Lam) : ((2u << __builtin_ctz((uint32_t)i)) - (uint32_t)Lam);
+    }
+    const uint32_t old = atomicAdd(lane == 0 ? &cnt32[i >> 2] : &dummy[lane],
+                                   lane == 0 ? (1u << (8 * (i & 3))) : 0u);
+
+    int top;
+    if (cont) {
+      top = __builtin_ctz((uint32_t)i);
+    } else {
+      const uint32_t nu = lane < W ? prow[p] : 0u;
+      int A = LOGN, d = 0;
+      if (wl >= 0) {
+        const int lim = wl < i ? wl : i;
+        const uint32_t x = (ucur ^ nu) & prefix_mask(lane, lim);
+        const uint64_t bx = ballot(x != 0u);
+        if (bx == 0ull) {
+          d = lim;
+        } else {
+          const int w = __builtin_ctzll(bx);
+          d = w * 32 + __builtin_ctz(readlane(x, w));
+        }
+        A = (wl == i) ? 0 : msb((uint32_t)(wl ^ i)) + 1;
+        if (A < wlam) A = wlam;  // stages below the last node's stage were not computed
+      }
+      const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
+      top = (A > Bm ? A : Bm) - 1;
+      ucur = nu;
+    }
+    if (top < lam) top = lam;
+    uint32_t xa = node_alpha<LOGN, TR, STATS>(top, lam, i, ucur, root, al, dummy, lane, n_fg);
+    // the node's values: up to 64 one per lane in xa, more in LDS at vals[0, 2^lam); a node
+    // that is the whole code holds the channel LLRs, copied into the (free) tree memory
+    uint32_t* vals = al + (Lam - 1);
+    if (lam == LOGN) {
+      if (Lam > kWave) {
+        for (int e = lane; e < N; e += kWave) al[e] = TR::load(root, e);
+        lds_order();
+        vals = al;
+      } else {
+        xa = TR::load(root, lane < Lam ? lane : Lam - 1);
+      }
+    } else if (Lam == kWave) {
+      xa = vals[lane];
+    }
+    const bool wide = Lam > 32;  // the node covers whole words
+    const uint32_t ppm = (uint32_t)(pk >> 32);
+
+    // ---- hard decisions of the node, re-encoded into the u domain ------------------
+    const int wi = i >> 5;
+    uint32_t hdw = 0u;   // node of <= 32 leaves: u bits, bit e = position i + e
+    uint32_t ublk = 0u;  // wider node: lane-per-word u bits of the node's words
+    bool inb = false;    // lane holds one of the node's words
+    if (!wide) {
+      hdw = (uint32_t)ballot(lane < Lam && TR::hd(xa));
+      for (int s2 = 0; s2 < lam; ++s2) hdw ^= (hdw >> (1 << s2)) & kLowMask[s2];
+    } else {
+      inb = lane >= wi && lane < wi + (Lam >> 5);
+      uint32_t v = 0u;
+      for (int r = 0; r < (Lam >> 6); ++r) {
+        const uint64_t b = ballot(TR::hd(Lam == kWave ? xa : vals[r * kWave + lane]));
+        const int w0 = wi + 2 * r;
+        v = lane == w0 ? (uint32_t)b : (lane == w0 + 1 ? (uint32_t)(b >> 32) : v);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 5; ++s2) v ^= (v >> (1 << s2)) & kLowMask[s2];
+      for (int s2 = 5; s2 < lam; ++s2) {
+        const int dw = 1 << (s2 - 5);
+        const uint32_t y = xor_lane_rt(v, dw);
+        if (!((lane - wi) & dw)) v ^= y;
+      }
+      ublk = v;
+    }
+    // parity of the hard decisions = u_0 of the node (row 0 of the transform is all ones)
+    const int parity = wide ? (int)(readlane(ublk, wi) & 1u) : (int)(hdw & 1u);
+
+    // ---- candidates (Section 2.2.4) -------------------------------------------------
+    // candidate c: metric kpm[c]; for R-1 / SPC the flipped least reliable positions as a
+    // mask over m[0..3]; for REP whether it is the all-ones word
+    int nk = 0;
+    uint32_t kpm[8];
+    uint32_t kflip[8];
+    int m[4] = {0, 0, 0, 0};
+    if (cls == kNodeR0 || cls == kNodeRep) {
+      uint32_t s0 = 0u, s1 = 0u;
+      node_sums<TR>(lam, xa, vals, lane, s0, s1);
+      kpm[0] = TR::pm_add(ppm, s0);
+      kflip[0] = 0u;
+      nk = 1;
+      if (cls == kNodeRep) {
+        kpm[1] = TR::pm_add(ppm, s1);
+        kflip[1] = 1u;
+        nk = 2;
+      }
+    } else {
+      const int nlr = cls == kNodeR1 ? (lam >= 1 ? 2 : 1) : 4;
+      const uint32_t magr = TR::mag(xa);
+      if (Lam > kWave) {  // magnitudes in place of the values (not needed again)
+        for (int e = lane; e < Lam; e += kWave) vals[e] = TR::mag(vals[e]);
+        lds_order();
+      }
+      uint32_t mm[4] = {0u, 0u, 0u, 0u};
+      for (int k = 0; k < nlr; ++k) {
+        m[k] = node_argmin(lam, &magr, vals, m, k, lane, false);
+        mm[k] = Lam <= kWave ? readlane(magr, m[k]) : vals[m[k]];
+      }
+      for (int f = 0; f < (1 << nlr); ++f) {
+        if (cls == kNodeSpc && (__builtin_popcount((uint32_t)f) & 1) != parity) continue;
+        uint32_t pm = ppm;
+        for (int k = 0; k < nlr; ++k)
+          if (f & (1 << k)) pm = TR::pm_add(pm, mm[k]);
+        kpm[nk] = pm;
+        kflip[nk] = (uint32_t)f;
+        ++nk;
+      }
+    }
+    // u bits of candidate c: R-0 all 0; REP all 0 or (re-encoded all-ones) a 1 at the last
+    // position; R-1 / SPC u(HD) xor the subsets of every flipped position
+    auto cand_block = [&](int c) -> NodeBlock {
+      NodeBlock b;
+      if (!wide) {
+        uint32_t x;
+        if (cls == kNodeR0) {
+          x = 0u;
+        } else if (cls == kNodeRep) {
+          x = kflip[c] ? (1u << (Lam - 1)) : 0u;
+        } else {
+          x = hdw;
+          for (int k = 0; k < 4; ++k)
+            if (kflip[c] & (1u << k)) x ^= subsets32(m[k]);
+        }
+        const uint32_t fm = (Lam == 32 ? 0xFFFFFFFFu : ((1u << Lam) - 1u)) << (i & 31);
+        b.in = lane == wi;
+        b.word = (ucur & ~fm) | (x << (i & 31));
+      } else {
+        uint32_t x;
+        if (cls == kNodeR0) {
+          x = 0u;
+        } else if (cls == kNodeRep) {
+          x = (kflip[c] && lane == wi + (Lam >> 5) - 1) ? 0x80000000u : 0u;
+        } else {
+          x = ublk;
+          for (int k = 0; k < 4; ++k)
+            if (kflip[c] & (1u << k)) {
+              const int mw = m[k] >> 5;
+              x ^= (((lane - wi) & ~mw) == 0) ? subsets32(m[k]) : 0u;
+            }
+        }
+        b.in = inb;
+        b.word = x;
+      }
+      return b;
+    };
+
+    // ---- children onto the stack ----------------------------------------------------
+    const uint32_t seq0 = next_seq;
+    next_seq += (uint32_t)nk;
+    const uint32_t lo0 = key_lo(N, i + Lam, seq0);
+    const NodeBlock b0 = cand_block(0);
+    const uint64_t k0 = make_key(kpm[0], lo0);
+    prow[b0.in ? p : kMaxD] = b0.word;
+    s_key = (lane == p) ? k0 : s_key;
+    vmask |= 1ull << p;
+    if (k0 > maxk) {
+      maxk = k0;
+      max_slot = p;
+    }
+    for (int c = 1; c < nk; ++c) {
+      const uint64_t kc = make_key(kpm[c], lo0 + (uint32_t)c);
+      int t = -1;
+      if (__builtin_popcountll(vmask) < D) {
+        t = __builtin_ctzll(~vmask & dmask);
+        if (kc > maxk) {
+          maxk = kc;
+          max_slot = t;
+        }
+      } else {
+        if (maxk == kNone) {
+          const bool lv = (vmask >> lane) & 1ull;
+          const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
+          const uint32_t Mh = wave_max(xh);
+          const uint64_t tq = ballot(xh == Mh) & vmask;
+          uint32_t Ml;
+          if (__builtin_popcountll(tq) == 1) {
+            max_slot = __builtin_ctzll(tq);
+            Ml = readlane((uint32_t)s_key, max_slot);
+          } else {
+            const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
+            Ml = wave_max(xl);
+            max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
+          }
+          maxk = make_key(Mh, Ml);
+        }
+        if (kc < maxk) {
+          t = max_slot;
+          maxk = kNone;
+          if constexpr (STATS) ++n_ev;
+        } else {
+          if constexpr (STATS) ++n_dr;
+        }
+      }
+      if (t >= 0) {
+        const NodeBlock bc = cand_block(c);
+        prow[lane < W ? t : kMaxD] = bc.in ? bc.word : ucur;
+        s_key = (lane == t) ? kc : s_key;
+        vmask |= 1ull << t;
+        if (kc < lb) lb = kc;
+      }
+    }
+    ucur = b0.in ? b0.word : ucur;
+    lds_order();
+
+    if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
+      if constexpr (STATS) ++n_pr;
+      vmask &= ~ballot(((uint32_t)s_key >> kSeqBits) >= (uint32_t)(N - i));
+      maxk = kNone;
+    }
+    wl = i;
+    wlam = lam;
+    c_lo = seq0;
+    c_hi = seq0 + (uint32_t)nk;
+    cand = k0;
+    cand_slot = p;
+  }
+
+  if (lane < W) {
+    uint32_t iw = infow;
+    int k = code.pre[lane];
+    uint8_t* dst = job.payload;
+    while (iw) {
+      const int b = __builtin_ctz(iw);
+      iw &= iw - 1u;
+      if (k < code.kp) dst[k] = (uint8_t)((st ? (out >> b) : 0u) & 1u);
+      ++k;
+    }
+  }
+  if (lane == 0) *job.status = (uint8_t)st;
+  if constexpr (STATS) {
+    const uint32_t v[8] = {n_it, n_sw, n_cp, n_sc, n_fg, n_ev, n_dr, n_pr};
+    if (lane < 8) {
+      uint32_t x = v[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) x = lane == j ? v[j] : x;
+      reinterpret_cast<uint32_t*>(job.stats)[lane] = x;
+    }
+  }
+}
+
+template <int LOGN, class TR, bool STATS>
+__global__ __launch_bounds__(256) void fsscs_uniform_kernel(CodeArgs code, int D, int L,
+                                                            const typename TR::In* __restrict__ llr,
+                                                            int64_t n_frames,
+                                                            uint8_t* __restrict__ payload,
+                                                            uint8_t* __restrict__ status,
+                                                            scs_stats* __restrict__ stats,
+                                                            int wave_words) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t frame = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (frame >= n_frames) return;
+  constexpr int N = 1 << LOGN;
+  FrameJob job;
+  job.llr = llr + frame * N;
+  job.payload = payload + frame * code.kp;
+  job.status = status + frame;
+  job.stats = STATS ? stats + frame : nullptr;
+  job.D = D;
+  job.L = L;
+  fsscs_frame<LOGN, TR, STATS>(code, job, lds + wave * wave_words);
+}
+
+template <class TR, bool STATS>
+using FsscsKernel = void (*)(CodeArgs, int, int, const typename TR::In*, int64_t, uint8_t*,
+                             uint8_t*, scs_stats*, int);
+
+template <class TR, bool STATS>
+FsscsKernel<TR, STATS> fsscs_kernel_for(int logn) {
+  switch (logn) {
+    case 1: return fsscs_uniform_kernel<1, TR, STATS>;
+    case 2: return fsscs_uniform_kernel<2, TR, STATS>;
+    case 3: return fsscs_uniform_kernel<3, TR, STATS>;
+    case 4: return fsscs_uniform_kernel<4, TR, STATS>;
+    case 5: return fsscs_uniform_kernel<5, TR, STATS>;
+    case 6: return fsscs_uniform_kernel<6, TR, STATS>;
+    case 7: return fsscs_uniform_kernel<7, TR, STATS>;
+    case 8: return fsscs_uniform_kernel<8, TR, STATS>;
+    case 9: return fsscs_uniform_kernel<9, TR, STATS>;
+    case 10: return fsscs_uniform_kernel<10, TR, STATS>;
+    case 11: return fsscs_uniform_kernel<11, TR, STATS>;
+    default: return nullptr;
+  }
+}
+
+template <class TR>
+hipError_t launch_fsscs_t(const polarscs::FsscsLaunch& a) {
+  const int N = a.code.N;
+  const int wave_words = lds_words_per_wave(N, a.D);
+  const int wpb = a.waves_per_block;
+  const size_t lds = (size_t)wpb * wave_words * 4;
+  const int64_t blocks = (a.n_frames + wpb - 1) / wpb;
+  (void)hipGetLastError();  // drop an error left by an earlier call of another library
+  if (a.stats) {
+    auto k = fsscs_kernel_for<TR, true>(a.code.logn);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.D,
+                       a.L, (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status,
+                       a.stats, wave_words);
+  } else {
+    auto k = fsscs_kernel_for<TR, false>(a.code.logn);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.D,
+                       a.L, (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status,
+                       a.stats, wave_words);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace polarscs {
+
+hipError_t launch_fsscs(const FsscsLaunch& a) {
+  return a.dtype == SCS_LLR_F32 ? launch_fsscs_t<TrF32>(a) : launch_fsscs_t<TrI8>(a);
+}
+
+}  // namespace polarscs

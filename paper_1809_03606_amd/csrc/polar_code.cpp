@@ -75,6 +75,36 @@ uint16_t crc16_payload(const uint8_t* bits, int nbits) {
 
 }  // namespace polarscs
 
+namespace polarscs {
+
+// Split the leaves [first, first + 2^lambda) into fast-decoding nodes, left to right: a
+// block whose leaves are all frozen (R-0), all information (R-1), information only at the
+// last leaf (REP, two or more leaves) or frozen only at the first leaf (SPC, four or more
+// leaves) is one node; any other block is split in halves.  A leaf is R-0 or R-1.
+static void split_nodes(polar_code* c, int first, int lam) {
+  const int size = 1 << lam;
+  int k = 0;
+  for (int j = first; j < first + size; ++j) k += c->info[j];
+  int cls = -1;
+  if (k == 0) cls = 0;
+  else if (k == size) cls = 1;
+  else if (size >= 2 && k == 1 && c->info[first + size - 1]) cls = 2;
+  else if (size >= 4 && k == size - 1 && !c->info[first]) cls = 3;
+  if (cls >= 0) {
+    c->nodes[first] = (uint8_t)((cls << 4) | lam);
+    return;
+  }
+  split_nodes(c, first, lam - 1);
+  split_nodes(c, first + size / 2, lam - 1);
+}
+
+void build_node_table(polar_code* c) {
+  c->nodes.assign((size_t)c->N, 0xFF);
+  split_nodes(c, 0, c->logn);
+}
+
+}  // namespace polarscs
+
 using polarscs::crc16_payload;
 
 extern "C" {
@@ -159,6 +189,7 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_d
             (uint16_t)(c->crc_syn[(size_t)b * 256 + (v & (v - 1))] ^ (pos < N ? share[pos] : 0));
       }
   }
+  polarscs::build_node_table(c);
   *out = c;
   return POLAR_OK;
 }

@@ -21,10 +21,14 @@ struct polar_code {
   // the CRC syndrome (payload bit: its unit remainder; CRC bit: its place in the register).
   // A vector passes the check when the xor over its bytes is 0.  Empty without a CRC.
   std::vector<uint16_t> crc_syn;
+  // Fast simplified schedule (Sections 2.2.2 and 3): nodes[i] = (class << 4) | lambda for
+  // the first leaf i of every node, 0xFF elsewhere.  Classes: 0 R-0, 1 R-1, 2 REP, 3 SPC.
+  std::vector<uint8_t> nodes;
   int32_t payload_bits() const { return K - crc; }
   int32_t words() const { return N >= 32 ? N / 32 : 1; }
 };
 
 namespace polarscs {
 uint16_t crc16_payload(const uint8_t* bits, int nbits);
+void build_node_table(polar_code* c);
 }

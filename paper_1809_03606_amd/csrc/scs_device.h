@@ -16,6 +16,7 @@ struct CodeArgs {
   uint32_t info[64];
   uint16_t pre[64];
   const uint16_t* crc_tab;  // device copy of polar_code::crc_syn (null without a CRC)
+  const uint8_t* nodes;     // device copy of polar_code::nodes (fast simplified decoder)
 };
 
 inline CodeArgs make_args(const polar_code* c) {

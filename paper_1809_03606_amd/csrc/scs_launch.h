@@ -20,6 +20,21 @@ struct RowsLaunch {
   hipStream_t stream;
 };
 
+struct FsscsLaunch {
+  CodeArgs code;  // nodes and crc_tab set
+  int D, L, dtype;
+  int waves_per_block;
+  const void* llr;
+  int64_t n_frames;
+  uint8_t* payload;
+  uint8_t* status;
+  scs_stats* stats;
+  hipStream_t stream;
+};
+
+// Enqueue the fast simplified stack decoder (one frame per wavefront).
+hipError_t launch_fsscs(const FsscsLaunch& a);
+
 // LDS bytes of one workgroup of the several-frames-per-wavefront kernel.
 size_t rows_lds_bytes(int N, int D, int G, int waves_per_block);
 // Enqueue the several-frames-per-wavefront decoder.

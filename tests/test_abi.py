@@ -137,3 +137,22 @@ def test_library_shares_pytorchs_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 64, 256, 1024, 2048])
+def test_library_schedule_matches_oracle(lib, N):
+    """The fast decoder's node table, built by the library, equals the oracle's schedule,
+    including the degenerate codes whose root is a node (K = 1, N - 1, N)."""
+    rng = np.random.default_rng(N)
+    Ks = sorted({1, max(1, N - 1), N, N // 2, int(rng.integers(1, N + 1))})
+    for K in Ks:
+        crc = 16 if K > 16 and N >= 64 else 0
+        code = binding.PolarCode(N, K, crc, 2.0)
+        assert binding.polar_code_schedule(code.handle) == oracle.fssc_schedule(code.info_mask), (N, K)
+
+
+def test_fsscs_rejects_bad_arguments(lib):
+    code = binding.PolarCode(64, 32, 0)
+    assert lib.fsscs_decode_batch(None, code.handle, 8, 8, 0, None, 1, None, None, None,
+                                  None) == binding.POLAR_EINVAL
+    assert lib.polar_code_schedule(None, None) == binding.POLAR_EINVAL

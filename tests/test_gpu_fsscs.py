@@ -1,0 +1,65 @@
+"""GPU parity of the fast simplified stack decoder (FSSCS-RM, Section 4) with the oracle,
+frame by frame: payload bits, status and the search itself (node extensions, switches,
+completions, SC-schedule work, evictions, drops, prunes)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from cases import THREADS, assert_parity, gpu_decode, make_frames
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(cuda, N, K, crc, D, L, eb, B, seed, dtype="f32"):
+    from paper_1809_03606_amd.binding import PolarCode
+
+    label = "FSSCS N=%d K=%d crc=%d D=%d L=%d Eb/N0=%.1f B=%d seed=%d %s" % (
+        N, K, crc, D, L, eb, B, seed, dtype)
+    info, pay, llr = make_frames(N, K, crc, eb, B, seed, dtype=dtype)
+    code = PolarCode(N, K, crc, 2.0)
+    assert (code.info_mask == info).all()
+    mode = oracle.F32 if dtype == "f32" else oracle.FIX
+    ref = oracle.fsscs_decode_batch(mode, info, crc, D, L, llr, threads=THREADS)
+    _say("gpu: " + label)
+    got = gpu_decode(cuda, code, D, L, llr, fast=True)
+    assert_parity(got, ref, label)
+    return got, ref, pay
+
+
+# every length; CRC on and off; D 1..64, L 1..255; degenerate codes whose root is a node
+# (K = 1: REP, K = N - 1: SPC, K = N: R-1); batches not a multiple of the workgroup size
+CASES = [
+    (2, 1, 0, 1, 1, 1.0), (2, 2, 0, 4, 8, 0.0), (4, 3, 0, 4, 8, 1.0), (8, 4, 0, 8, 8, 0.5),
+    (16, 8, 0, 64, 255, 0.0), (16, 15, 0, 5, 3, 1.0), (32, 24, 16, 16, 8, 2.0),
+    (32, 1, 0, 3, 2, 0.0), (64, 32, 0, 8, 8, 2.0), (64, 64, 0, 8, 4, 3.0),
+    (64, 48, 16, 32, 4, 1.0), (128, 64, 16, 64, 8, 1.5), (128, 127, 0, 8, 8, 2.0),
+    (256, 128, 16, 32, 8, 1.5), (256, 1, 0, 4, 4, 0.0), (512, 256, 16, 64, 8, 1.5),
+    (512, 511, 0, 8, 8, 3.0), (1024, 512, 16, 32, 8, 1.5), (1024, 853, 16, 64, 16, 2.5),
+    (1024, 1024, 0, 8, 8, 4.0), (2048, 1024, 16, 32, 8, 1.5), (2048, 1707, 16, 64, 8, 3.0),
+    (2048, 2047, 0, 4, 4, 4.0), (2048, 1, 0, 4, 4, 0.0),
+]
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", CASES)
+def test_fsscs_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=31 + N)
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", CASES[::2])
+def test_fsscs_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=41 + N, dtype="i8")
+
+
+@pytest.mark.parametrize("eb", [1.0, 2.0, 3.0])
+def test_fsscs_n1024_crc16_points(cuda, eb):
+    """PC(1024,512)+CRC-16, D = 32, L = 8 at three Eb/N0 points, 400 frames each."""
+    got, ref, pay = _run(cuda, 1024, 512, 16, 32, 8, eb, 400, seed=int(eb * 10))
