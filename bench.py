@@ -59,10 +59,14 @@ def parse():
                     help="lanes per frame (0: the autotuner's choice, see --tune)")
     ap.add_argument("--wpb", type=int, default=0, choices=(0, 1, 2, 4),
                     help="wavefronts per workgroup (0: the autotuner's choice)")
+    ap.add_argument("--decoder", choices=("scs", "fsscs"), default="scs",
+                    help="scs: successive-cancellation stack decoding (the headline); fsscs: "
+                         "fast simplified stack decoding (FSSCS-RM) on the same frames")
     ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
                     help="launch-shape autotuner: use the cached choice or tune once (auto), "
                          "always re-tune (force), or use the library's defaults (off)")
-    ap.add_argument("--workload", choices=("sweep", "mixed", "serve", "fixed"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "mixed", "serve", "fixed", "depth"),
+                    default="sweep",
                     help="sweep: PC(1024,512) headline; mixed: 25 codes / 3 depths in one launch; "
                          "serve: Poisson requests through the continuous-batching server")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -181,6 +185,9 @@ def write_trace_summary(trace_dir, bench_json, out_md):
     """Markdown summary of a kernel trace of `python bench.py --cpu-sample 0`: per-kernel
     statistics, and the decoder's mean duration beside bench.py's own HIP-event mean."""
     rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    decoder = b["roofline"]["kernel"].split("<")[0]
     per = {}
     for r in rows:
         name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
@@ -188,12 +195,12 @@ def write_trace_summary(trace_dir, bench_json, out_md):
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
         per.setdefault(short[:90], []).append(d)
     total = sum(sum(v) for v in per.values())
-    with open(bench_json) as fh:
-        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
-    lines = ["# Kernel trace: SCS decoder, PC(1024,512)+CRC-16 sweep", "",
+    title = "FSSCS-RM" if decoder.startswith("fsscs") else "SCS"
+    extra = " --decoder fsscs" if decoder.startswith("fsscs") else ""
+    lines = ["# Kernel trace: %s decoder, PC(1024,512)+CRC-16 sweep" % title, "",
              "Command (from the repository root on one MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
-             "python bench.py --cpu-sample 0", "",
+             "python bench.py%s --cpu-sample 0" % extra, "",
              "Workload: N=1024, K=512 (496 payload + 16 CRC), D=32, L=8, Eb/N0 1.0/1.5/2.0/2.5/3.0 "
              "dB, %d frames per point, launch shape %s.  Decoder launches: one counter launch "
              "per point (stats variant), %d warmup and %d timed steps of one launch per point.  "
@@ -205,8 +212,8 @@ def write_trace_summary(trace_dir, bench_json, out_md):
     for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:8]:
         lines.append("| %s | %d | %.3f | %.3f | %.3f | %.2f%% |" % (
             k, len(v), np.mean(v), min(v), max(v), 100.0 * sum(v) / total))
-    dec = [d for k, v in per.items() if DECODER in k for d in v]
-    timed = [d for k, v in per.items() if DECODER in k and ", true>" not in k for d in v]
+    dec = [d for k, v in per.items() if k.startswith(decoder) for d in v]
+    timed = [d for k, v in per.items() if k.startswith(decoder) and ", true>" not in k for d in v]
     lines += ["", "Decoder mean over all %d launches (points mixed): %.1f ms.  Without the counter "
               "launches (%d warmup + timed launches): %.1f ms.  bench.py's HIP-event mean over its "
               "timed launches: %.1f ms (`roofline.mean_launch_ms`); bench value %.1f Mbit/s." % (
@@ -247,11 +254,11 @@ def main():
             sys.exit(2)
         {"mixed": run_mixed, "serve": run_serve}[args.workload](args)
         return
-    if args.workload == "fixed":
+    if args.workload in ("fixed", "depth"):
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
             sys.exit(2)
-        run_fixed(args)
+        {"fixed": run_fixed, "depth": run_depth}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
@@ -276,12 +283,13 @@ def main():
     if not (args.lanes or args.wpb) and args.tune != "off":
         from paper_1809_03606_amd import tune
 
-        entry = None if args.tune == "force" else tune.apply(ctx, code, D, L, args.dtype)
+        dec = args.decoder
+        entry = None if args.tune == "force" else tune.apply(ctx, code, D, L, args.dtype, decoder=dec)
         source = "cache"
         if entry is None:
             t0 = time.time()
-            entry = tune.tune(code, D, L, args.dtype)
-            tune.apply(ctx, code, D, L, args.dtype)
+            entry = tune.tune(code, D, L, args.dtype, decoder=dec)
+            tune.apply(ctx, code, D, L, args.dtype, decoder=dec)
             source = "tuned in %.1f s" % (time.time() - t0)
         launch_shape = {"lanes_per_frame": entry["lanes_per_frame"],
                         "waves_per_block": entry["waves_per_block"], "source": source,
@@ -317,8 +325,11 @@ def main():
     out_st = torch.empty((B,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((B, 8), dtype=torch.int32, device=dev)
 
+    fast = args.decoder == "fsscs"
+    decode_fn = binding.fsscs_decode_batch if fast else binding.scs_decode_batch
+
     def launch(llr, with_stats=False):
-        binding.scs_decode_batch(ctx.handle, code.handle, D, L, llr_dtype, llr, B, out_pay,
+        decode_fn(ctx.handle, code.handle, D, L, llr_dtype, llr, B, out_pay,
                                  out_st, stats if with_stats else None, stream)
 
     # -- per-point work counters and FER (untimed) ------------------------------------
@@ -384,8 +395,9 @@ def main():
     achieved = ops_per_launch / mean_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                "frac": achieved / peak, "traffic": measured_traffic(B),
-                "kernel": ("scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
+                "frac": achieved / peak, "traffic": None if fast else measured_traffic(B),
+                "kernel": ("fsscs_uniform_kernel" if fast else
+                           "scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
                            else "scs_rows_kernel<%d>" % launch_shape["lanes_per_frame"])
                           + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
                 "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch}
@@ -404,10 +416,11 @@ def main():
         for eb, pay, llr in data:
             x = llr[:n].contiguous()
             c0 = time.perf_counter()
-            rp, rs, _ = oracle.scs_decode_batch(mode, info, CRC, D, L, x.cpu().numpy(), threads=thr)
+            ofn = oracle.fsscs_decode_batch if fast else oracle.scs_decode_batch
+            rp, rs, _ = ofn(mode, info, CRC, D, L, x.cpu().numpy(), threads=thr)
             t += time.perf_counter() - c0
             # the same sample on the GPU must give the same bits
-            binding.scs_decode_batch(ctx.handle, code.handle, D, L, llr_dtype, x, n, out_pay,
+            decode_fn(ctx.handle, code.handle, D, L, llr_dtype, x, n, out_pay,
                                      out_st, None, stream)
             stream.synchronize()
             match &= bool(np.array_equal(out_pay[:n].cpu().numpy(), rp) and
@@ -420,12 +433,14 @@ def main():
                "seconds": t, "gpu_matches_oracle_on_sample": match}
 
     line = {
-        "metric": "info Mbit/s decoded (N=1024,K=512,D=32) at oracle-matched FER; p99 latency",
+        "metric": "info Mbit/s decoded (N=1024,K=512,D=32) at oracle-matched FER; p99 latency"
+                  + ("; FSSCS-RM decoder" if fast else ""),
         "value": value, "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
-        "config": {"workload": "SCS sweep PC(1024,512)+CRC16 D=32 L=8 Eb/N0 1.0-3.0 dB",
+        "config": {"workload": ("FSSCS-RM" if fast else "SCS")
+                               + " sweep PC(1024,512)+CRC16 D=32 L=8 Eb/N0 1.0-3.0 dB",
                    "N": N, "K": K, "crc_bits": CRC, "D": D, "L": L,
                    "ebn0_db": points, "frames_per_point": B, "global_batch": B * len(points),
                    "launches_per_step": len(points), "parallelism": "single GPU",
@@ -644,6 +659,70 @@ def run_fixed(args):
         "fer_i8": e8 / B, "fer_i8_ci95": wilson(e8, B),
         "fer_f32": e32 / B, "fer_f32_ci95": wilson(e32, B),
         "f32_payload_mbps": B * kp / (ms32 * 1e-3) / 1e6,
+    }
+    print(json.dumps(line))
+
+
+def run_depth(args):
+    """Stack depth and L: FER and throughput of SCS and FSSCS-RM on the same 10^6 noisy
+    frames of PC(1024,512)+CRC-16 at 2 dB (and 3 dB), for D in {8, 16, 32, 64} (one stack slot
+    per lane) and L in {2, 4, 8}."""
+    import torch
+
+    from paper_1809_03606_amd import binding, channel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    B, kp = args.frames, K - CRC
+    code = binding.PolarCode(N, K, CRC, 2.0)
+    ctx = binding.ScsContext(0, 64, 0)
+    stream = torch.cuda.Stream(device=dev)
+    out = torch.empty((B, kp), dtype=torch.uint8, device=dev)
+    st = torch.empty((B,), dtype=torch.uint8, device=dev)
+    rows = []
+    for pi, eb in enumerate([float(x) for x in args.points.split(",")]):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(SEED * 1000 + 7 + pi)
+        pay = channel.device_payload(torch, gen, B, kp, dev)
+        llr = torch.empty((B, N), dtype=torch.float32, device=dev)
+        chunk = 1 << 17
+        for lo in range(0, B, chunk):
+            hi = min(B, lo + chunk)
+            cw = torch.empty((hi - lo, N), dtype=torch.uint8, device=dev)
+            code.encode_device(pay[lo:hi], cw)
+            llr[lo:hi] = channel.device_llr(torch, gen, cw, eb, K / N, "f32")
+            del cw
+        torch.cuda.synchronize()
+        for dec in ("scs", "fsscs"):
+            fn = binding.fsscs_decode_batch if dec == "fsscs" else binding.scs_decode_batch
+            for d in (8, 16, 32, 64):
+                for Lp in (2, 4, 8):
+                    fn(ctx.handle, code.handle, d, Lp, binding.SCS_LLR_F32, llr, B, out, st,
+                       None, stream)  # warm-up
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    fn(ctx.handle, code.handle, d, Lp, binding.SCS_LLR_F32, llr, B, out, st,
+                       None, stream)
+                    b.record(stream)
+                    stream.synchronize()
+                    ms = a.elapsed_time(b)
+                    errs = int((out != pay).any(dim=1).sum().item())
+                    rows.append({"decoder": dec, "ebn0_db": eb, "D": d, "L": Lp, "fer": errs / B,
+                                 "fer_ci95": wilson(errs, B), "launch_ms": ms,
+                                 "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
+                    log("depth: %s Eb/N0 %.1f D=%d L=%d FER %.5f %.0f Mbit/s" % (
+                        dec, eb, d, Lp, errs / B, rows[-1]["payload_mbps"]))
+        del llr, pay
+    ref = [r for r in rows if r["decoder"] == "scs" and r["D"] == D and r["L"] == L]
+    line = {
+        "metric": "FER and info Mbit/s vs stack depth D and L, SCS and FSSCS-RM",
+        "value": ref[0]["payload_mbps"] if ref else None, "unit": "Mbit/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
+        "config": {"workload": "depth study PC(1024,512)+CRC16, D in {8,16,32,64}, L in {2,4,8}",
+                   "frames": B},
+        "rows": rows,
     }
     print(json.dumps(line))
 

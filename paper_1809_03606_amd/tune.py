@@ -36,8 +36,15 @@ def _arch(torch) -> str:
         return "unknown"
 
 
-def key(arch: str, code, D: int, L: int, dtype: str) -> str:
-    return "%s:N%d:K%d:crc%d:D%d:L%d:%s" % (arch, code.N, code.K, code.crc_bits, D, L, dtype)
+def key(arch: str, code, D: int, L: int, dtype: str, decoder: str = "scs") -> str:
+    k = "%s:N%d:K%d:crc%d:D%d:L%d:%s" % (arch, code.N, code.K, code.crc_bits, D, L, dtype)
+    return k if decoder == "scs" else k + ":" + decoder
+
+
+def candidates(decoder: str = "scs"):
+    """Launch shapes: (lanes per frame, wavefronts per workgroup).  The fast decoder has
+    the one-frame-per-wavefront form only."""
+    return CANDIDATES if decoder == "scs" else [c for c in CANDIDATES if c[0] == 64]
 
 
 def _read(path: str) -> dict:
@@ -67,7 +74,8 @@ def save(entries: dict, path: str | None = None):
 
 
 def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames: int = 65536,
-         reps: int = 2, seed: int = 7, path: str | None = None, verbose: bool = False) -> dict:
+         reps: int = 2, seed: int = 7, path: str | None = None, verbose: bool = False,
+         decoder: str = "scs") -> dict:
     """Time every launch shape on `frames` noisy frames; store and return the best."""
     import torch
 
@@ -85,13 +93,14 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
     stream = torch.cuda.Stream(device=dev)
     times = {}
     ref = None
-    for lanes, wpb in CANDIDATES:
+    fast = decoder == "fsscs"
+    for lanes, wpb in candidates(decoder):
         ctx.configure(lanes, wpb)
         ms = []
         for r in range(reps + 1):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            ctx.decode(code, D, L, llr, out, st, None, stream)
+            ctx.decode(code, D, L, llr, out, st, None, stream, fast=fast)
             b.record(stream)
             stream.synchronize()
             if r:
@@ -102,24 +111,26 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
             raise RuntimeError("launch shape %s changed the decoded bits" % ((lanes, wpb),))
         times["%d/%d" % (lanes, wpb)] = min(ms)
         if verbose:
-            print("tune %s lanes=%d wpb=%d: %.2f ms" % (key("", code, D, L, dtype), lanes, wpb, min(ms)))
+            print("tune %s lanes=%d wpb=%d: %.2f ms" % (key("", code, D, L, dtype, decoder), lanes,
+                                                         wpb, min(ms)))
     best = min(times, key=times.get)
     lanes, wpb = (int(x) for x in best.split("/"))
     entry = {"lanes_per_frame": lanes, "waves_per_block": wpb, "ms": times[best],
              "candidates_ms": times, "frames": frames, "ebn0_db": ebn0_db,
              "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
     entries = _read(path or cache_path())
-    entries[key(_arch(torch), code, D, L, dtype)] = entry
+    entries[key(_arch(torch), code, D, L, dtype, decoder)] = entry
     save(entries, path)
     ctx.close()
     return entry
 
 
-def apply(ctx, code, D: int, L: int, dtype: str = "f32", path: str | None = None) -> dict | None:
+def apply(ctx, code, D: int, L: int, dtype: str = "f32", path: str | None = None,
+          decoder: str = "scs") -> dict | None:
     """Configure `ctx` with the cached best launch shape, if any; returns the entry."""
     import torch
 
-    entry = load(path).get(key(_arch(torch), code, D, L, dtype))
+    entry = load(path).get(key(_arch(torch), code, D, L, dtype, decoder))
     if entry:
         ctx.configure(entry["lanes_per_frame"], entry["waves_per_block"])
     return entry
@@ -139,11 +150,12 @@ def main(argv=None):
     ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
     ap.add_argument("--ebn0", type=float, default=2.0)
     ap.add_argument("--frames", type=int, default=65536)
+    ap.add_argument("--decoder", choices=("scs", "fsscs"), default="scs")
     ap.add_argument("--out", default=None, help="cache file (default: the user cache)")
     a = ap.parse_args(argv)
     code = binding.PolarCode(a.N, a.K, a.crc, 2.0)
     entry = tune(code, a.D, a.L, a.dtype, ebn0_db=a.ebn0, frames=a.frames, path=a.out,
-                 verbose=True)
+                 verbose=True, decoder=a.decoder)
     print(json.dumps(entry))
 
 
