@@ -60,6 +60,10 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   // needs no ordering across lanes; entry kMaxD takes the stores of lanes that must not
   // store.
   uint32_t prow[kMaxD + 1];
+  // Every stored row is zero past its path's length (rows are written whole from a tree
+  // path that is zero there, or gain a single 1 at the decided position), so a decision of
+  // 0 needs no store.  The empty path's row starts at zero.
+  prow[0] = 0u;
   uint32_t* cnt32 = lds;               // N bytes: extensions per length
   uint32_t* al = cnt32 + (N + 3) / 4;  // N - 1 words: alpha stages 0 .. n-1
   uint32_t* dummy = al + N;            // kWave words: stores of lanes that must not store
@@ -190,7 +194,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       const int Bm = (d >= i) ? 0 : msb((uint32_t)(i ^ d)) + 1;
       top = (A > Bm ? A : Bm) - 1;
       if (top < 0) top = 0;
-      ucur = nu;
+      ucur = nu & prefix_mask(lane, i);  // the tree path is zero past its length
     }
     uint32_t a0;
     if (cont && top <= LY::SMALL) {
@@ -210,9 +214,10 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     next_seq += info ? 2u : 1u;
     const int wi = i >> 5;
     const uint32_t bitm = 1u << (i & 31);
-    // bit i of the tree's path may hold a stale bit of the slot's previous occupant
-    ucur = (lane == wi) ? ((ucur & ~bitm) | (info && h ? bitm : 0u)) : ucur;
-    prow[lane == wi ? p : kMaxD] = ucur;
+    if (info && h) {  // a decided 1 (a 0 is already there)
+      ucur = (lane == wi) ? (ucur | bitm) : ucur;
+      prow[lane == wi ? p : kMaxD] = ucur;
+    }
     s_key = (lane == p) ? k0 : s_key;
     vmask |= 1ull << p;
     if (k0 > maxk) {  // never true while the worst key is unknown
