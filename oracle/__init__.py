@@ -81,10 +81,15 @@ def lib():
             L.orc_fsscs_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                                  ctypes.c_int64, vp, vp, vp]
+            L.orc_scl_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                         vp, vp, vp, vp, vp]
+            L.orc_scl_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
+                                               ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp]
             for name in ("orc_construct", "orc_bhattacharyya_log", "orc_polar_transform",
                          "orc_encode_batch", "orc_sc_decode", "orc_scs_decode",
                          "orc_scs_decode_batch", "orc_ml_decode", "orc_fssc_schedule",
-                         "orc_node_candidates", "orc_fsscs_decode", "orc_fsscs_decode_batch"):
+                         "orc_node_candidates", "orc_fsscs_decode", "orc_fsscs_decode_batch",
+                         "orc_scl_decode", "orc_scl_decode_batch"):
                 getattr(L, name).restype = ctypes.c_int
             del u8p
             _lib = L
@@ -276,6 +281,51 @@ def fsscs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, 
         return L_.orc_fsscs_decode_batch(mode, N, _p(info), int(crc_bits), int(D), int(L),
                                          int(types), _p(a[lo:hi]), hi - lo, _p(pay[lo:hi]),
                                          _p(status[lo:hi]), _p(stats[lo:hi]))
+
+    threads = max(1, min(int(threads), B if B else 1))
+    if threads == 1:
+        _check(run(0, B))
+    else:
+        edges = np.linspace(0, B, threads + 1).astype(int)
+        with ThreadPoolExecutor(threads) as ex:
+            for rc in ex.map(lambda t: run(edges[t], edges[t + 1]), range(threads)):
+                _check(rc)
+    return pay, status, stats
+
+
+def scl_decode(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr):
+    """CA-SCL decoding of one frame (Section 2.2.3).  Returns (u_hat, status, pm, stats)."""
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    a = _llr_array(mode, llr)
+    u = np.zeros(info.size, np.uint8)
+    st = ctypes.c_uint8(0)
+    pm = ctypes.c_double(0.0)
+    s = _Stats()
+    _check(lib().orc_scl_decode(mode, int(info.size), _p(info), int(crc_bits), int(L), _p(a),
+                                _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s)))
+    return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
+
+
+def scl_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr,
+                     threads: int = 1):
+    """Decode frames llr[B][N] with CA-SCL; returns (payload[B][K-r], status[B], stats[B])."""
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    a = _llr_array(mode, llr)
+    N = int(info.size)
+    a = a.reshape(-1, N)
+    B = a.shape[0]
+    k = int(info.sum()) - int(crc_bits)
+    pay = np.zeros((B, k), np.uint8)
+    status = np.zeros(B, np.uint8)
+    stats = np.zeros(B, STATS_DTYPE)
+    L_ = lib()
+
+    def run(lo, hi):
+        if hi <= lo:
+            return 0
+        return L_.orc_scl_decode_batch(mode, N, _p(info), int(crc_bits), int(L), _p(a[lo:hi]),
+                                       hi - lo, _p(pay[lo:hi]), _p(status[lo:hi]),
+                                       _p(stats[lo:hi]))
 
     threads = max(1, min(int(threads), B if B else 1))
     if threads == 1:

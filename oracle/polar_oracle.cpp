@@ -744,6 +744,112 @@ int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int t
   return 0;
 }
 
+// ---------------------------------------------------------------------------------
+// Successive-cancellation list decoding with CRC selection (CA-SCL), Section 2.2.3, with
+// one alpha/beta tree per list entry (Section 3.2 keeps L trees; lazy copying is an
+// optimisation of the same computation and is not reproduced here: a surviving child
+// simply copies its parent's tree).
+//
+// Readings:
+//  - the list starts with one path of metric 0; at a frozen leaf every path takes u = 0
+//    and its metric grows by |alpha| when HD(alpha) = 1 (eq. PMupd); at an information
+//    leaf every path l (in list order) offers two candidates, u = 0 then u = 1, each with
+//    the metric of eq. (PMupd); the min(2 n, L) candidates with the smallest key (metric,
+//    then candidate number 2 l + u) survive and form the new list in ascending key order.
+//  - selection (the CRC aid of Section 2.2.3): the paths are taken in ascending (metric,
+//    list position); the first whose information bits pass the CRC is the output (status
+//    OK); if none passes (or there is no CRC) the first path is the output, with status
+//    FALLBACK when a CRC was checked and failed for every path.
+//  - statistics: iterations = leaf estimates (paths x leaves), completions = CRC checks.
+// ---------------------------------------------------------------------------------
+template <class A>
+struct ListPath {
+  typename A::PM pm;
+  Tree<A> tree;
+  std::vector<uint8_t> u;
+};
+
+template <class A>
+int scl_decode_t(int n, const uint8_t* info, int crc_bits, int L, const void* llr,
+                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st) {
+  typedef typename A::PM PM;
+  const int N = 1 << n;
+  orc_stats s;
+  std::memset(&s, 0, sizeof s);
+  std::vector<ListPath<A>> list(1);
+  list[0].pm = PM(0);
+  list[0].tree.init(n, llr);
+  list[0].u.assign(N, 0);
+  for (int i = 0; i < N; ++i) {
+    std::vector<typename A::T> a(list.size());
+    for (size_t l = 0; l < list.size(); ++l) {
+      list[l].tree.calc_alpha(0, i);  // Algorithm 1 on the path's own tree
+      a[l] = list[l].tree.leaf();
+      ++s.iterations;
+    }
+    if (!info[i]) {
+      for (size_t l = 0; l < list.size(); ++l) {
+        if (A::hd(a[l])) list[l].pm = A::pm_add(list[l].pm, A::mag(a[l]));
+        list[l].u[i] = 0;
+        list[l].tree.set_leaf(i, 0);
+      }
+      continue;
+    }
+    // candidates 2 l + u, metric of eq. (PMupd)
+    struct C {
+      PM pm;
+      int idx;
+    };
+    std::vector<C> cand;
+    for (size_t l = 0; l < list.size(); ++l)
+      for (int u = 0; u < 2; ++u) {
+        PM m = list[l].pm;
+        if (u != A::hd(a[l])) m = A::pm_add(m, A::mag(a[l]));
+        cand.push_back(C{m, (int)(2 * l + u)});
+      }
+    std::stable_sort(cand.begin(), cand.end(), [](const C& x, const C& y) {
+      return x.pm < y.pm || (!(y.pm < x.pm) && x.idx < y.idx);
+    });
+    const size_t keep = std::min(cand.size(), (size_t)L);
+    std::vector<ListPath<A>> next;
+    for (size_t k = 0; k < keep; ++k) {
+      const int l = cand[k].idx >> 1, u = cand[k].idx & 1;
+      ListPath<A> c = list[(size_t)l];  // the parent's tree, copied
+      c.pm = cand[k].pm;
+      c.u[i] = (uint8_t)u;
+      c.tree.set_leaf(i, (uint8_t)u);
+      next.push_back(std::move(c));
+    }
+    list.swap(next);
+  }
+  std::vector<size_t> order(list.size());
+  for (size_t l = 0; l < order.size(); ++l) order[l] = l;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return list[x].pm < list[y].pm; });
+  size_t out = order[0];
+  uint8_t stat = ORC_ST_OK;
+  if (crc_bits) {
+    stat = ORC_ST_FALLBACK;
+    for (size_t q : order) {
+      ++s.completions;
+      if (crc_passes(N, info, crc_bits, list[q].u.data())) {
+        out = q;
+        stat = ORC_ST_OK;
+        break;
+      }
+    }
+  }
+  for (auto& p : list) {
+    s.f_ops += p.tree.f_ops;
+    s.g_ops += p.tree.g_ops;
+  }
+  std::memcpy(u_hat, list[out].u.data(), (size_t)N);
+  if (pm_out) *pm_out = (double)list[out].pm;
+  *status = stat;
+  if (st) *st = s;
+  return 0;
+}
+
 // Bhattacharyya parameters in the log domain (R17): z0 = exp(-R * Eb/N0) for BPSK on
 // AWGN; the "minus" (f) child of z is 2z - z^2 and the "plus" (g) child is z^2.
 // Indices: the children of index j are 2j (minus) and 2j+1 (plus), so the first split
@@ -990,6 +1096,41 @@ int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bi
     int rc = orc_fsscs_decode(mode, N, info_mask, crc_bits, D, L, types,
                               (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
                               nullptr, st ? st + b : nullptr);
+    if (rc) return rc;
+    int q = 0;
+    for (int j = 0; j < N && q < k; ++j)
+      if (info_mask[j]) payload[b * k + q++] = u[j];
+  }
+  return 0;
+}
+
+int orc_scl_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
+                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                   orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  switch (mode) {
+    case ORC_F32: return scl_decode_t<ArF32>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
+    case ORC_F64: return scl_decode_t<ArF64>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
+    case ORC_FIX: return scl_decode_t<ArFix>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
+  }
+  return -1;
+}
+
+int orc_scl_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
+                         const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
+                         orc_stats* st) {
+  const int n = log2_exact(N);
+  if (n < 0) return -1;
+  const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
+  int K = 0;
+  for (int j = 0; j < N; ++j) K += info_mask[j] ? 1 : 0;
+  const int k = K - crc_bits;
+  std::vector<uint8_t> u(N);
+  for (int64_t b = 0; b < B; ++b) {
+    int rc = orc_scl_decode(mode, N, info_mask, crc_bits, L,
+                            (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
+                            nullptr, st ? st + b : nullptr);
     if (rc) return rc;
     int q = 0;
     for (int j = 0; j < N && q < k; ++j)

@@ -1,6 +1,6 @@
 /*
  * polar_oracle.h -- plain CPU reference ("oracle") for polar-code construction,
- * encoding, SC, SCS and fast simplified stack (FSSCS-RM) decoding.
+ * encoding, SC, SCS, fast simplified stack (FSSCS-RM) and list (CA-SCL) decoding.
  *
  * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP decoder.  Only the
  * test suite, the smoke check and the benchmark's CPU-baseline leg may load it; the
@@ -106,6 +106,15 @@ int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, in
 int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
                            int L, int types, const void* llr, int64_t B, uint8_t* payload,
                            uint8_t* status, orc_stats* st);
+
+/* CA-SCL decoding of one frame (Section 2.2.3): list size L, CRC selection among the final
+ * paths (status OK, or FALLBACK when every path fails the CRC). */
+int orc_scl_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
+                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                   orc_stats* st);
+int orc_scl_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
+                         const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
+                         orc_stats* st);
 
 /* Brute-force ML over all 2^K information words (K <= 20): discrepancy
  * disc(c) = sum_{j: c_j != HD(llr_j)} |llr_j| in binary64.  Returns the minimum in
