@@ -201,6 +201,22 @@ int fsscs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t 
                        uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
                        void* hip_stream);
 
+/* CA-SCL decoding (Section 2.2.3): successive cancellation keeping a list of L paths (L = 1,
+ * 2, 4 or 8).  At a frozen position every path takes 0 and its metric grows by |alpha| when
+ * the hard decision is 1 (eq. PMupd); at an information position every path l (in list
+ * order) offers u = 0 and u = 1 (candidate numbers 2 l and 2 l + 1), and the L candidates
+ * with the smallest (metric, candidate number) form the new list in that order.  At the end
+ * the paths are taken in ascending (metric, list position) and the first that passes the
+ * CRC is the output (status SCS_STATUS_OK); if none passes, the first path with status
+ * SCS_STATUS_FALLBACK.  Without a CRC the best path, status OK.  Buffers and statistics as
+ * scs_decode_batch (iterations = path extensions, L per leaf once the list is full;
+ * completions = CRC checks; the other counters 0).  Errors: POLAR_EINVAL for another L or a
+ * bad argument; POLAR_EUNSUPPORTED when the L trees of one frame exceed 64 KB of LDS
+ * (N = 2048 with L = 8). */
+int scl_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t L, int32_t llr_dtype,
+                     const void* llr_dev, int64_t n_frames, uint8_t* payload_dev,
+                     uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream);
+
 /* Last HIP error seen by a call on this context (POLAR_OK if none), then cleared. */
 int scs_ctx_last_error(scs_ctx* ctx);
 

@@ -26,7 +26,7 @@ EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_enco
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
            "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
-           "polar_code_schedule", "fsscs_decode_batch")
+           "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
                 "drops", "prunes")
@@ -91,13 +91,14 @@ def lib():
             L.scs_ctx_set_waves_per_block.argtypes = [vp, i32]
             L.polar_code_schedule.argtypes = [vp, vp]
             L.fsscs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
+            L.scl_decode_batch.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, vp]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
                       "scs_ctx_set_waves_per_block", "scs_ctx_last_error",
-                      "polar_code_schedule", "fsscs_decode_batch"):
+                      "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -190,6 +191,13 @@ def fsscs_decode_batch(ctx: int, code: int, D: int, L: int, llr_dtype: int, llr_
     _check(lib().fsscs_decode_batch(ctx, code, int(D), int(L), int(llr_dtype), _addr(llr_dev),
                                     int(n_frames), _addr(payload_dev), _addr(status_dev),
                                     _addr(stats_dev), _stream(stream)), "fsscs_decode_batch")
+
+
+def scl_decode_batch(ctx: int, code: int, L: int, llr_dtype: int, llr_dev, n_frames: int,
+                     payload_dev, status_dev, stats_dev=None, stream=None):
+    _check(lib().scl_decode_batch(ctx, code, int(L), int(llr_dtype), _addr(llr_dev),
+                                  int(n_frames), _addr(payload_dev), _addr(status_dev),
+                                  _addr(stats_dev), _stream(stream)), "scl_decode_batch")
 
 
 def polar_code_schedule(handle: int) -> list:
@@ -302,6 +310,16 @@ class ScsContext:
         fn = fsscs_decode_batch if fast else scs_decode_batch
         fn(self.handle, code.handle, D, L, dtype, llr_dev, n, payload_dev, status_dev, stats_dev,
            stream)
+
+    def decode_list(self, code: PolarCode, L: int, llr_dev, payload_dev, status_dev,
+                    stats_dev=None, stream=None):
+        """CA-SCL decoding of llr_dev (frames x N) with a list of L paths."""
+        import torch
+
+        dtype = SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8
+        n = llr_dev.numel() // code.N
+        scl_decode_batch(self.handle, code.handle, L, dtype, llr_dev, n, payload_dev, status_dev,
+                         stats_dev, stream)
 
     def close(self):
         if self.handle:

@@ -1,0 +1,319 @@
+// Successive-cancellation list decoding with CRC selection (CA-SCL) on gfx950.
+//
+// Method: Aurora & Gross, Section 2.2.3 (SCL with the path metric of eq. PMupd, the CRC
+// selecting among the final list) with one alpha tree per list entry (Section 3.2).
+//
+// Mapping: one wavefront per frame; the L list entries (L = 1, 2, 4 or 8) share the 64
+// lanes, G = 64 / L lanes each, and every stage of the SC schedule is computed for all
+// entries at once (value e of entry p in lane p G + (e mod G)).  LDS holds, per physical
+// slot, the alpha tree (stage s at word offset 2^s - 1; the channel LLRs are read from the
+// input) and the decided bits u (N bits); a list position points to a slot.  At an
+// information leaf the 2n candidates (entry l with u = 0, then u = 1) sit in lanes; each
+// finds its rank by key (metric, candidate number) and the L best form the new list in
+// rank order.  A parent's first surviving child keeps the parent's slot; any other child
+// takes a free slot and copies the parent's alpha stages that later leaves read (above
+// stage ctz(i + 1)) and its bits.  Partial sums of a g-node are the transform of the left
+// sibling's decided bits (scratch words per entry for blocks of 64 bits and more).
+#include <hip/hip_runtime.h>
+
+#include "polarscs.h"
+#include "scs_device.h"
+#include "scs_launch.h"
+#include "scs_tree.h"
+
+namespace {
+
+// LDS words per wave of the list decoder: alpha trees and bit rows of L slots, sibling
+// scratch, candidate exchange, dummy words.
+__host__ __device__ inline int scl_words_per_wave(int N, int L) {
+  const int W = N >= 32 ? N / 32 : 1;
+  const int SW = N >= 128 ? N / 64 : 1;  // words of the largest sibling block (N / 2 bits)
+  return L * N + L * W + L * SW + 4 * 16 + kWave;
+}
+
+template <int LOGN, class TR, bool STATS>
+__device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& job, int L,
+                                          uint32_t* lds) {
+  constexpr int N = 1 << LOGN;
+  constexpr int W = N >= 32 ? N / 32 : 1;
+  constexpr int SW = N >= 128 ? N / 64 : 1;
+  const int lane = lane_id();
+  const int lgL = 31 - __builtin_clz((uint32_t)L);
+  const int lgG = 6 - lgL;
+  const int G = 1 << lgG;
+  const int mypos = lane >> lgG, myj = lane & (G - 1);
+  const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
+  uint32_t* A = lds;                 // L x N: alpha of slot q at A + q N
+  uint32_t* U = A + L * N;           // L x W: decided bits of slot q
+  uint32_t* SIB = U + L * W;         // L x SW: sibling partial sums of list entry p
+  uint32_t* XC = SIB + L * SW;       // 4 x 16: candidate exchange
+  uint32_t* dummy = XC + 64;         // kWave words
+
+  for (int j = lane; j < L * W; j += kWave) U[j] = 0u;
+  lds_order();
+
+  int n = 1;                         // list size
+  uint32_t pm = 0u;                  // lane p < n: metric of list entry p
+  uint32_t phys = lane < L ? (uint32_t)lane : 0u;  // lane p: slot of list entry p
+  uint32_t myslot = (uint32_t)__builtin_amdgcn_ds_bpermute(mypos << 2, (int)phys);
+  uint32_t n_it = 0, n_cp = 0;
+  const uint32_t infow = lane < W ? code.info[lane] : 0u;
+
+  for (int i = 0; i < N; ++i) {
+    const int top = i == 0 ? LOGN - 1 : __builtin_ctz((uint32_t)i);
+    const bool active = mypos < n;
+    // ---- the SC schedule for every list entry: stages top .. 0 ---------------------
+    for (int s = top; s >= 0; --s) {
+      const int Lam = 1 << s;
+      const bool odd = (i >> s) & 1;
+      const int base = ((i >> s) - 1) << s;  // left sibling block (odd nodes)
+      uint32_t sw = 0u;                       // blocks of <= 32 bits: transformed word
+      if (odd) {
+        if (Lam <= 32) {
+          uint32_t x = U[myslot * W + (base >> 5)] >> (base & 31);
+          if (Lam < 32) x &= (1u << Lam) - 1u;
+          for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+          sw = x;
+        } else {
+          const int nw = Lam >> 5;
+          // in-word transforms of the block's words, then across words, per entry
+          for (int j = myj; j < nw; j += G) {
+            uint32_t x = U[myslot * W + (base >> 5) + j];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+            *(active ? &SIB[mypos * SW + j] : &dummy[lane]) = x;
+          }
+          lds_order();
+          for (int d = 1; d < nw; d <<= 1) {
+            for (int j = myj; j < nw; j += G) {
+              const uint32_t y = (j & d) ? 0u : SIB[mypos * SW + j + d];
+              if (active && !(j & d)) SIB[mypos * SW + j] ^= y;
+            }
+            lds_order();
+          }
+        }
+      }
+      const int R = Lam > G ? (Lam >> lgG) : 1;
+      uint32_t* dst = A + myslot * N + (Lam - 1);
+      const uint32_t* src = A + myslot * N + (2 * Lam - 1);
+      for (int r = 0; r < R; ++r) {
+        const int e = r * G + myj;
+        const bool ok = active && e < Lam;
+        const int ee = ok ? e : 0;
+        uint32_t a, b;
+        if (s + 1 == LOGN) {
+          a = TR::load(root, ee);
+          b = TR::load(root, ee + Lam);
+        } else {
+          a = src[ee];
+          b = src[ee + Lam];
+        }
+        uint32_t v;
+        if (!odd) {
+          v = TR::f(a, b);
+        } else {
+          const uint32_t word = Lam <= 32 ? sw : SIB[mypos * SW + (ee >> 5)];
+          v = TR::g(a, b, (word >> (ee & 31)) & 1u);
+        }
+        *(ok ? &dst[ee] : &dummy[lane]) = v;
+      }
+      lds_order();
+    }
+    // ---- leaf decision for every entry ------------------------------------------------
+    const uint32_t a0 = lane < n ? A[phys * N] : 0u;
+    const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
+    if constexpr (STATS) n_it += (uint32_t)n;
+    if (!info) {
+      if (lane < n && TR::hd(a0)) pm = TR::pm_add(pm, TR::mag(a0));
+      continue;  // u_i = 0 is already in every row
+    }
+    // candidates c = 2 l + u in lanes c < 2n
+    const int nc = 2 * n;
+    const int cl = lane >> 1, cu = lane & 1;
+    const uint32_t ca = (uint32_t)__builtin_amdgcn_ds_bpermute(cl << 2, (int)a0);
+    const uint32_t cpm0 = (uint32_t)__builtin_amdgcn_ds_bpermute(cl << 2, (int)pm);
+    const bool chd = TR::hd(ca);
+    const uint32_t cpm = (lane < nc && (cu != 0) != chd) ? TR::pm_add(cpm0, TR::mag(ca)) : cpm0;
+    // rank by (metric, candidate number)
+    int rank = 0;
+    for (int c = 0; c < nc; ++c) {
+      const uint32_t o = readlane(cpm, c);
+      rank += (o < cpm || (o == cpm && c < lane)) ? 1 : 0;
+    }
+    const int n2 = nc < L ? nc : L;
+    // survivors: scatter (parent, bit, metric) to their new positions
+    const bool surv = lane < nc && rank < n2;
+    *(surv ? &XC[rank] : &dummy[lane]) = (uint32_t)(cl << 1 | cu);
+    *(surv ? &XC[16 + rank] : &dummy[lane]) = cpm;
+    lds_order();
+    const uint32_t pc = lane < n2 ? XC[lane] : 0u;        // new entry k: 2 parent + bit
+    const uint32_t npm = lane < n2 ? XC[16 + lane] : 0u;
+    const int par = (int)(pc >> 1);
+    const uint32_t pslot = (uint32_t)__builtin_amdgcn_ds_bpermute(par << 2, (int)phys);
+    // the first child (lowest new position) of each parent keeps the parent's slot
+    uint64_t first = 0ull, used = 0ull;
+    for (int l = 0; l < n; ++l) {
+      const uint64_t m = ballot(lane < n2 && par == l);
+      if (m) {
+        first |= m & (~m + 1ull);
+        used |= 1ull << readlane(phys, l);
+      }
+    }
+    const bool isfirst = (first >> lane) & 1ull;
+    const uint64_t others = ballot(lane < n2 && !isfirst);
+    const uint32_t freeslots = (uint32_t)(~used) & ((1u << L) - 1u);
+    // a non-first child takes the k-th free slot, k = its rank among non-first children
+    uint32_t nslot = pslot;
+    if (lane < n2 && !isfirst) {
+      int k = __builtin_popcountll(others & ((1ull << lane) - 1ull));
+      uint32_t f = freeslots;
+      for (int q = 0; q < k; ++q) f &= f - 1u;
+      nslot = f ? (uint32_t)__builtin_ctz(f) : 0u;  // never empty: n2 <= L
+    }
+    // copies for non-first children: alpha stages read later, and the bit row
+    const int keep_from = (i + 1 < N) ? (2 << __builtin_ctz((uint32_t)(i + 1))) - 1 : N;
+    uint64_t todo = others;
+    while (todo) {
+      const int k = __builtin_ctzll(todo);
+      todo &= todo - 1ull;
+      const uint32_t from = readlane(pslot, k), to = readlane(nslot, k);
+      for (int w = keep_from + lane; w < N - 1; w += kWave) A[to * N + w] = A[from * N + w];
+      for (int w = lane; w < W; w += kWave) U[to * W + w] = U[from * W + w];
+    }
+    lds_order();
+    // bit i of every surviving entry
+    if (lane < n2 && (pc & 1u)) atomicOr(&U[nslot * W + (i >> 5)], 1u << (i & 31));
+    lds_order();
+    n = n2;
+    pm = lane < n ? npm : 0u;
+    phys = lane < n ? nslot : phys;
+    // unused slots keep their numbers in lanes >= n (only lanes < n are read)
+    myslot = (uint32_t)__builtin_amdgcn_ds_bpermute(mypos << 2, (int)phys);
+  }
+
+  // ---- selection: entries in ascending (metric, position); first to pass the CRC -------
+  int order = 0;
+  for (int c = 0; c < n; ++c) {
+    const uint32_t o = readlane(pm, c);
+    order += (o < pm || (o == pm && c < lane)) ? 1 : 0;
+  }
+  uint32_t st = SCS_STATUS_OK;
+  int out = __builtin_ctzll(ballot(lane < n && order == 0));
+  if (code.crc) {
+    st = SCS_STATUS_FALLBACK;
+    for (int q = 0; q < n; ++q) {
+      const int p = __builtin_ctzll(ballot(lane < n && order == q));
+      const uint32_t slot = readlane(phys, p);
+      const uint32_t row = lane < W ? U[slot * W + lane] : 0u;
+      if constexpr (STATS) ++n_cp;
+      if (crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
+        out = p;
+        st = SCS_STATUS_OK;
+        break;
+      }
+    }
+  }
+  const uint32_t oslot = readlane(phys, out);
+  const uint32_t orow = lane < W ? U[oslot * W + lane] : 0u;
+  if (lane < W) {
+    uint32_t iw = infow;
+    int k = code.pre[lane];
+    uint8_t* dstp = job.payload;
+    while (iw) {
+      const int b = __builtin_ctz(iw);
+      iw &= iw - 1u;
+      if (k < code.kp) dstp[k] = (uint8_t)((orow >> b) & 1u);
+      ++k;
+    }
+  }
+  if (lane == 0) *job.status = (uint8_t)st;
+  if constexpr (STATS) {
+    const uint32_t v[8] = {n_it, 0u, n_cp, 0u, 0u, 0u, 0u, 0u};
+    if (lane < 8) {
+      uint32_t x = v[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) x = lane == j ? v[j] : x;
+      reinterpret_cast<uint32_t*>(job.stats)[lane] = x;
+    }
+  }
+}
+
+template <int LOGN, class TR, bool STATS>
+__global__ __launch_bounds__(256) void scl_uniform_kernel(CodeArgs code, int L,
+                                                          const typename TR::In* __restrict__ llr,
+                                                          int64_t n_frames,
+                                                          uint8_t* __restrict__ payload,
+                                                          uint8_t* __restrict__ status,
+                                                          scs_stats* __restrict__ stats,
+                                                          int wave_words) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t frame = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (frame >= n_frames) return;
+  constexpr int N = 1 << LOGN;
+  FrameJob job;
+  job.llr = llr + frame * N;
+  job.payload = payload + frame * code.kp;
+  job.status = status + frame;
+  job.stats = STATS ? stats + frame : nullptr;
+  job.D = 0;
+  job.L = L;
+  scl_frame<LOGN, TR, STATS>(code, job, L, lds + wave * wave_words);
+}
+
+template <class TR, bool STATS>
+using SclKernel = void (*)(CodeArgs, int, const typename TR::In*, int64_t, uint8_t*, uint8_t*,
+                           scs_stats*, int);
+
+template <class TR, bool STATS>
+SclKernel<TR, STATS> scl_kernel_for(int logn) {
+  switch (logn) {
+    case 1: return scl_uniform_kernel<1, TR, STATS>;
+    case 2: return scl_uniform_kernel<2, TR, STATS>;
+    case 3: return scl_uniform_kernel<3, TR, STATS>;
+    case 4: return scl_uniform_kernel<4, TR, STATS>;
+    case 5: return scl_uniform_kernel<5, TR, STATS>;
+    case 6: return scl_uniform_kernel<6, TR, STATS>;
+    case 7: return scl_uniform_kernel<7, TR, STATS>;
+    case 8: return scl_uniform_kernel<8, TR, STATS>;
+    case 9: return scl_uniform_kernel<9, TR, STATS>;
+    case 10: return scl_uniform_kernel<10, TR, STATS>;
+    case 11: return scl_uniform_kernel<11, TR, STATS>;
+    default: return nullptr;
+  }
+}
+
+template <class TR>
+hipError_t launch_scl_t(const polarscs::SclLaunch& a) {
+  const int wave_words = scl_words_per_wave(a.code.N, a.L);
+  const int wpb = a.waves_per_block;
+  const size_t lds = (size_t)wpb * wave_words * 4;
+  const int64_t blocks = (a.n_frames + wpb - 1) / wpb;
+  (void)hipGetLastError();  // drop an error left by an earlier call of another library
+  if (a.stats) {
+    auto k = scl_kernel_for<TR, true>(a.code.logn);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.L,
+                       (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status, a.stats,
+                       wave_words);
+  } else {
+    auto k = scl_kernel_for<TR, false>(a.code.logn);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.L,
+                       (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status, a.stats,
+                       wave_words);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace polarscs {
+
+size_t scl_lds_bytes(int N, int L) { return (size_t)scl_words_per_wave(N, L) * 4; }
+
+hipError_t launch_scl(const SclLaunch& a) {
+  return a.dtype == SCS_LLR_F32 ? launch_scl_t<TrF32>(a) : launch_scl_t<TrI8>(a);
+}
+
+}  // namespace polarscs

@@ -754,6 +754,43 @@ int fsscs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t 
   return POLAR_OK;
 }
 
+int scl_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t L, int32_t llr_dtype,
+                     const void* llr_dev, int64_t n_frames, uint8_t* payload_dev,
+                     uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream) {
+  if (!ctx || !code) return POLAR_EINVAL;
+  if (L != 1 && L != 2 && L != 4 && L != 8) return POLAR_EINVAL;
+  if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
+  if (n_frames < 0) return POLAR_EINVAL;
+  if (n_frames == 0) return POLAR_OK;
+  if (!llr_dev || !status_dev || (!payload_dev && code->payload_bits() > 0)) return POLAR_EINVAL;
+  if (code->logn < 1 || code->logn > 11) return POLAR_EUNSUPPORTED;
+  const size_t bytes = polarscs::scl_lds_bytes(code->N, L);
+  if (bytes > kMaxLdsPerBlock) return POLAR_EUNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
+  polarscs::SclLaunch a;
+  a.code = make_args(code);
+  if (const int e = device_table(code, kTabCrcSyn, &a.code.crc_tab)) return e;
+  int wpb = 1;
+  const int cap = ctx->wpb ? ctx->wpb : 4;
+  while (wpb < cap && (size_t)(wpb * 2) * bytes <= kMaxLdsPerBlock) wpb *= 2;
+  a.L = L;
+  a.dtype = llr_dtype;
+  a.waves_per_block = wpb;
+  a.llr = llr_dev;
+  a.n_frames = n_frames;
+  a.payload = payload_dev;
+  a.status = status_dev;
+  a.stats = stats_dev;
+  a.stream = (hipStream_t)hip_stream;
+  if ((n_frames + wpb - 1) / wpb > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
+  if (polarscs::launch_scl(a) != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->last_error = POLAR_EDEVICE;
+    return POLAR_EDEVICE;
+  }
+  return POLAR_OK;
+}
+
 int polar_code_schedule(const polar_code* code, uint8_t* nodes_out) {
   if (!code || !nodes_out) return POLAR_EINVAL;
   std::memcpy(nodes_out, code->nodes.data(), (size_t)code->N);

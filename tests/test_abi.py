@@ -156,3 +156,9 @@ def test_fsscs_rejects_bad_arguments(lib):
     assert lib.fsscs_decode_batch(None, code.handle, 8, 8, 0, None, 1, None, None, None,
                                   None) == binding.POLAR_EINVAL
     assert lib.polar_code_schedule(None, None) == binding.POLAR_EINVAL
+
+
+def test_scl_rejects_bad_arguments(lib):
+    code = binding.PolarCode(64, 32, 0)
+    assert lib.scl_decode_batch(None, code.handle, 8, 0, None, 1, None, None, None,
+                                None) == binding.POLAR_EINVAL

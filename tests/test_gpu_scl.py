@@ -1,0 +1,63 @@
+"""GPU parity of the CA-SCL list decoder (Section 2.2.3) with the oracle, frame by frame:
+payload bits, status, path extensions and CRC checks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from cases import THREADS, make_frames
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cuda, N, K, crc, L, eb, B, seed, dtype="f32"):
+    from paper_1809_03606_amd import binding
+
+    label = "SCL N=%d K=%d crc=%d L=%d Eb/N0=%.1f B=%d seed=%d %s" % (N, K, crc, L, eb, B, seed,
+                                                                      dtype)
+    info, pay, llr = make_frames(N, K, crc, eb, B, seed, dtype=dtype)
+    code = binding.PolarCode(N, K, crc, 2.0)
+    mode = oracle.F32 if dtype == "f32" else oracle.FIX
+    rp, rs, rst = oracle.scl_decode_batch(mode, info, crc, L, llr, threads=THREADS)
+    print("gpu: " + label, flush=True)
+    sys.stdout.flush()
+    dev = cuda.device("cuda", 0)
+    x = cuda.from_numpy(np.ascontiguousarray(llr)).to(dev)
+    gp = cuda.full((B, code.payload_bits), 0xEE, dtype=cuda.uint8, device=dev)
+    gs = cuda.full((B,), 0xEE, dtype=cuda.uint8, device=dev)
+    gst = cuda.zeros((B, 8), dtype=cuda.int32, device=dev)
+    ctx = binding.ScsContext(0)
+    ctx.decode_list(code, L, x, gp, gs, gst)
+    cuda.cuda.synchronize()
+    gp, gs = gp.cpu().numpy(), gs.cpu().numpy()
+    gst = gst.cpu().numpy().view(np.uint32)
+    ctx.close()
+    bad = np.nonzero((gp != rp).any(axis=1) | (gs != rs))[0]
+    assert bad.size == 0, "%s: %d frames differ, first %s" % (label, bad.size, bad[:8])
+    assert np.array_equal(gst[:, 0], rst["iterations"]), label
+    assert np.array_equal(gst[:, 2], rst["completions"]), label
+    return gp, pay
+
+
+CASES = [
+    (2, 1, 0, 1, 1.0), (2, 2, 0, 2, 0.0), (4, 3, 0, 4, 1.0), (8, 4, 0, 8, 0.5),
+    (16, 8, 0, 8, 0.0), (32, 24, 16, 4, 2.0), (64, 32, 0, 8, 2.0), (64, 48, 16, 2, 1.0),
+    (128, 64, 16, 8, 1.5), (256, 128, 16, 8, 1.5), (256, 200, 16, 4, 2.5),
+    (512, 256, 16, 8, 1.5), (1024, 512, 16, 8, 1.5), (1024, 853, 16, 1, 2.5),
+    (1024, 512, 16, 2, 1.0), (2048, 1024, 16, 4, 1.5), (2048, 1707, 16, 2, 3.0),
+]
+
+
+@pytest.mark.parametrize("N,K,crc,L,eb", CASES)
+def test_scl_matches_oracle_f32(cuda, N, K, crc, L, eb):
+    _run(cuda, N, K, crc, L, eb, 37 if N >= 1024 else 101, seed=51 + N)
+
+
+@pytest.mark.parametrize("N,K,crc,L,eb", CASES[1::2])
+def test_scl_matches_oracle_i8(cuda, N, K, crc, L, eb):
+    _run(cuda, N, K, crc, L, eb, 37 if N >= 1024 else 101, seed=61 + N, dtype="i8")
+
+
+def test_scl_n1024_l8_2db(cuda):
+    got, pay = _run(cuda, 1024, 512, 16, 8, 2.0, 400, seed=9)
