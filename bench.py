@@ -59,9 +59,10 @@ def parse():
                     help="lanes per frame (0: the autotuner's choice, see --tune)")
     ap.add_argument("--wpb", type=int, default=0, choices=(0, 1, 2, 4),
                     help="wavefronts per workgroup (0: the autotuner's choice)")
-    ap.add_argument("--decoder", choices=("scs", "fsscs"), default="scs",
+    ap.add_argument("--decoder", choices=("scs", "fsscs", "scl"), default="scs",
                     help="scs: successive-cancellation stack decoding (the headline); fsscs: "
-                         "fast simplified stack decoding (FSSCS-RM) on the same frames")
+                         "fast simplified stack decoding (FSSCS-RM); scl: CA-SCL with a list "
+                         "of L paths; all on the same frames")
     ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
                     help="launch-shape autotuner: use the cached choice or tune once (auto), "
                          "always re-tune (force), or use the library's defaults (off)")
@@ -195,8 +196,10 @@ def write_trace_summary(trace_dir, bench_json, out_md):
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
         per.setdefault(short[:90], []).append(d)
     total = sum(sum(v) for v in per.values())
-    title = "FSSCS-RM" if decoder.startswith("fsscs") else "SCS"
-    extra = " --decoder fsscs" if decoder.startswith("fsscs") else ""
+    title = ("FSSCS-RM" if decoder.startswith("fsscs") else
+             "CA-SCL" if decoder.startswith("scl") else "SCS")
+    extra = (" --decoder fsscs" if decoder.startswith("fsscs") else
+             " --decoder scl" if decoder.startswith("scl") else "")
     lines = ["# Kernel trace: %s decoder, PC(1024,512)+CRC-16 sweep" % title, "",
              "Command (from the repository root on one MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
@@ -280,7 +283,7 @@ def main():
     code = binding.PolarCode(N, K, CRC, 2.0)
     ctx = binding.ScsContext(0, args.lanes, args.wpb)
     launch_shape = {"lanes_per_frame": args.lanes, "waves_per_block": args.wpb, "source": "flags"}
-    if not (args.lanes or args.wpb) and args.tune != "off":
+    if not (args.lanes or args.wpb) and args.tune != "off" and args.decoder != "scl":
         from paper_1809_03606_amd import tune
 
         dec = args.decoder
@@ -326,7 +329,12 @@ def main():
     stats = torch.zeros((B, 8), dtype=torch.int32, device=dev)
 
     fast = args.decoder == "fsscs"
-    decode_fn = binding.fsscs_decode_batch if fast else binding.scs_decode_batch
+    scl = args.decoder == "scl"
+    if scl:
+        def decode_fn(ctx_h, code_h, D_, L_, dt, x, n, p_, s_, st_, strm):
+            binding.scl_decode_batch(ctx_h, code_h, L_, dt, x, n, p_, s_, st_, strm)
+    else:
+        decode_fn = binding.fsscs_decode_batch if fast else binding.scs_decode_batch
 
     def launch(llr, with_stats=False):
         decode_fn(ctx.handle, code.handle, D, L, llr_dtype, llr, B, out_pay,
@@ -340,7 +348,10 @@ def main():
         stream.synchronize()
         s = stats.cpu().numpy().view(np.uint32).astype(np.int64)
         it, sc = s[:, 0].sum(), s[:, 3].sum()
-        work_ops[eb] = OPS_PER_ELEM * sc + ops_per_iteration(D) * it
+        if scl:  # every list entry runs the SC schedule: N log2 N f/g values per entry
+            work_ops[eb] = OPS_PER_ELEM * (it / N) * N * int(np.log2(N)) + 8 * it
+        else:
+            work_ops[eb] = OPS_PER_ELEM * sc + ops_per_iteration(D) * it
         fer = float((out_pay != pay).any(dim=1).float().mean().item())
         log("work counters: Eb/N0 %.1f dB, FER %.2e, %.0f iterations/frame" % (eb, fer, it / B))
         per_point[eb] = {"fer": fer, "mean_iterations": float(it / B),
@@ -396,7 +407,7 @@ def main():
     peak = PEAK_LANE_OPS / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                 "frac": achieved / peak, "traffic": None if fast else measured_traffic(B),
-                "kernel": ("fsscs_uniform_kernel" if fast else
+                "kernel": ("fsscs_uniform_kernel" if fast else "scl_uniform_kernel" if scl else
                            "scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
                            else "scs_rows_kernel<%d>" % launch_shape["lanes_per_frame"])
                           + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
@@ -416,8 +427,11 @@ def main():
         for eb, pay, llr in data:
             x = llr[:n].contiguous()
             c0 = time.perf_counter()
-            ofn = oracle.fsscs_decode_batch if fast else oracle.scs_decode_batch
-            rp, rs, _ = ofn(mode, info, CRC, D, L, x.cpu().numpy(), threads=thr)
+            if scl:
+                rp, rs, _ = oracle.scl_decode_batch(mode, info, CRC, L, x.cpu().numpy(), threads=thr)
+            else:
+                ofn = oracle.fsscs_decode_batch if fast else oracle.scs_decode_batch
+                rp, rs, _ = ofn(mode, info, CRC, D, L, x.cpu().numpy(), threads=thr)
             t += time.perf_counter() - c0
             # the same sample on the GPU must give the same bits
             decode_fn(ctx.handle, code.handle, D, L, llr_dtype, x, n, out_pay,
@@ -434,12 +448,12 @@ def main():
 
     line = {
         "metric": "info Mbit/s decoded (N=1024,K=512,D=32) at oracle-matched FER; p99 latency"
-                  + ("; FSSCS-RM decoder" if fast else ""),
+                  + ("; FSSCS-RM decoder" if fast else "; CA-SCL decoder, list 8" if scl else ""),
         "value": value, "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
-        "config": {"workload": ("FSSCS-RM" if fast else "SCS")
+        "config": {"workload": ("FSSCS-RM" if fast else "CA-SCL" if scl else "SCS")
                                + " sweep PC(1024,512)+CRC16 D=32 L=8 Eb/N0 1.0-3.0 dB",
                    "N": N, "K": K, "crc_bits": CRC, "D": D, "L": L,
                    "ebn0_db": points, "frames_per_point": B, "global_batch": B * len(points),
