@@ -1,6 +1,6 @@
 """Full-size batches in the launch configuration the benchmark times (10^6 frames of
-PC(1024,512)+CRC-16, D=32, L=8, one launch), checked on a sample of frames against the
-oracle.  The batch is generated on the device; for the sampled frames the payload and the
+PC(1024,512)+CRC-16, D=32, L=8, one launch; for each of the three decoders), checked on a
+sample of frames against the oracle.  The batch is generated on the device; for the sampled frames the payload and the
 noise are copied back, encoded with the oracle's encoder and passed through the channel on
 the host, and those host LLRs (which must equal the device LLRs bit for bit) are what the
 oracle decodes."""
@@ -25,7 +25,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _full(cuda, ebn0, dtype, seed):
+def _full(cuda, ebn0, dtype, seed, decoder="scs"):
     from paper_1809_03606_amd import binding
 
     torch = cuda
@@ -54,8 +54,11 @@ def _full(cuda, ebn0, dtype, seed):
     out = torch.empty((FRAMES, kp), dtype=torch.uint8, device="cuda")
     st = torch.empty((FRAMES,), dtype=torch.uint8, device="cuda")
     ctx = binding.ScsContext(0)
-    _say("gpu: full-size %s batch at %.1f dB" % (dtype, ebn0))
-    ctx.decode(code, D, L, llr, out, st)
+    _say("gpu: full-size %s %s batch at %.1f dB" % (decoder, dtype, ebn0))
+    if decoder == "scl":
+        ctx.decode_list(code, L, llr, out, st)
+    else:
+        ctx.decode(code, D, L, llr, out, st, fast=decoder == "fsscs")
     torch.cuda.synchronize()
     idx = torch.from_numpy(sample).cuda()
     g_pay, g_st = out[idx].cpu().numpy(), st[idx].cpu().numpy()
@@ -70,10 +73,15 @@ def _full(cuda, ebn0, dtype, seed):
         h_llr = channel.bpsk_awgn_i8(cw_h, s_noise, ebn0, K / N)
         mode = oracle.FIX
     assert np.array_equal(h_llr.view(np.uint8), d_llr.view(np.uint8))
-    rp, rs, _ = oracle.scs_decode_batch(mode, info, CRC, D, L, h_llr, threads=THREADS)
+    if decoder == "scl":
+        rp, rs, _ = oracle.scl_decode_batch(mode, info, CRC, L, h_llr, threads=THREADS)
+    elif decoder == "fsscs":
+        rp, rs, _ = oracle.fsscs_decode_batch(mode, info, CRC, D, L, h_llr, threads=THREADS)
+    else:
+        rp, rs, _ = oracle.scs_decode_batch(mode, info, CRC, D, L, h_llr, threads=THREADS)
     assert np.array_equal(rp, g_pay) and np.array_equal(rs, g_st)
     fer = float((out != pay).any(dim=1).float().mean().item())
-    _say("full-size %s %.1f dB: FER %.4f" % (dtype, ebn0, fer))
+    _say("full-size %s %s %.1f dB: FER %.4f" % (decoder, dtype, ebn0, fer))
     return fer
 
 
@@ -84,3 +92,8 @@ def test_gpu_full_size_float32_sampled_against_oracle(cuda, ebn0):
 
 def test_gpu_full_size_fixed_point_sampled_against_oracle(cuda):
     _full(cuda, 2.0, "i8", seed=30)
+
+
+@pytest.mark.parametrize("decoder", ["fsscs", "scl"])
+def test_gpu_full_size_other_decoders_sampled_against_oracle(cuda, decoder):
+    _full(cuda, 2.0, "f32", seed=40, decoder=decoder)
