@@ -7,7 +7,8 @@
 // lanes, G = 64 / L lanes each, and every stage of the SC schedule is computed for all
 // entries at once (value e of entry p in lane p G + (e mod G)).  LDS holds, per physical
 // slot, the alpha tree (stage s at word offset 2^s - 1; the channel LLRs are read from the
-// input) and the decided bits u (N bits); a list position points to a slot.  At an
+// input; the top stage is kept once while it is the same for every entry) and the decided
+// bits u (N bits); a list position points to a slot.  At an
 // information leaf the 2n candidates (entry l with u = 0, then u = 1) sit in lanes; each
 // finds its rank by key (metric, candidate number) and the L best form the new list in
 // rank order.  A parent's first surviving child keeps the parent's slot; any other child
@@ -23,12 +24,16 @@
 
 namespace {
 
-// LDS words per wave of the list decoder: alpha trees and bit rows of L slots, sibling
-// scratch, candidate exchange, dummy words.
+// LDS words per wave of the list decoder: alpha stages below the top of L slots, bit rows
+// and top-stage partial sums of L slots, sibling scratch, the shared top stage, candidate
+// exchange, dummy words.
 __host__ __device__ inline int scl_words_per_wave(int N, int L) {
   const int W = N >= 32 ? N / 32 : 1;
   const int SW = N >= 128 ? N / 64 : 1;  // words of the largest sibling block (N / 2 bits)
-  return L * N + L * W + L * SW + 4 * 16 + kWave;
+  const int S = N >= 4 ? N / 2 : N;      // per-slot alpha words
+  const int TB = N >= 64 ? N / 64 : 1;   // top-stage partial sums
+  const int H = N >= 4 ? N / 2 : 0;      // shared top stage
+  return L * S + L * W + L * SW + L * TB + H + 4 * 16 + kWave;
 }
 
 template <int LOGN, class TR, bool STATS>
@@ -37,16 +42,26 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   constexpr int N = 1 << LOGN;
   constexpr int W = N >= 32 ? N / 32 : 1;
   constexpr int SW = N >= 128 ? N / 64 : 1;
+  // The top stage (N/2 values) is not kept per slot: before leaf N/2 it is f of the
+  // channel LLRs, the same for every entry (kept once); from leaf N/2 on it is g of the
+  // channel LLRs with the entry's partial sums of its first half (kept per slot, N/2 bits)
+  // and is recomputed when stage n-2 needs it (at leaves N/2 and 3N/4).
+  constexpr bool SPLIT = LOGN >= 2;
+  constexpr int H = N / 2;
+  constexpr int S = SPLIT ? H : N;
+  constexpr int TB = N >= 64 ? N / 64 : 1;
   const int lane = lane_id();
   const int lgL = 31 - __builtin_clz((uint32_t)L);
   const int lgG = 6 - lgL;
   const int G = 1 << lgG;
   const int mypos = lane >> lgG, myj = lane & (G - 1);
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
-  uint32_t* A = lds;                 // L x N: alpha of slot q at A + q N
-  uint32_t* U = A + L * N;           // L x W: decided bits of slot q
+  uint32_t* A = lds;                 // L x S: alpha of slot q at A + q S
+  uint32_t* U = A + L * S;           // L x W: decided bits of slot q
   uint32_t* SIB = U + L * W;         // L x SW: sibling partial sums of list entry p
-  uint32_t* XC = SIB + L * SW;       // 4 x 16: candidate exchange
+  uint32_t* TOPB = SIB + L * SW;     // L x TB: partial sums of the first half, slot q
+  uint32_t* TOPF = TOPB + L * TB;    // H: the top stage before leaf N/2 (shared)
+  uint32_t* XC = TOPF + (SPLIT ? H : 0);  // 4 x 16: candidate exchange
   uint32_t* dummy = XC + 64;         // kWave words
 
   for (int j = lane; j < L * W; j += kWave) U[j] = 0u;
@@ -67,6 +82,34 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       const int Lam = 1 << s;
       const bool odd = (i >> s) & 1;
       const int base = ((i >> s) - 1) << s;  // left sibling block (odd nodes)
+      if (SPLIT && s == LOGN - 1) {
+        if (!odd) {  // leaf 0: f of the channel LLRs, once for all entries
+          for (int e = lane; e < H; e += kWave) TOPF[e] = TR::f(TR::load(root, e), TR::load(root, e + H));
+        } else if (H <= 32) {  // leaf N/2: the entry's first-half partial sums
+          uint32_t x = U[myslot * W];
+          if (H < 32) x &= (1u << H) - 1u;
+          for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+          *(active && myj == 0 ? &TOPB[myslot * TB] : &dummy[lane]) = x;
+        } else {
+          const int nw = H >> 5;
+          for (int j = myj; j < nw; j += G) {
+            uint32_t x = U[myslot * W + j];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+            *(active ? &TOPB[myslot * TB + j] : &dummy[lane]) = x;
+          }
+          lds_order();
+          for (int d = 1; d < nw; d <<= 1) {
+            for (int j = myj; j < nw; j += G) {
+              const uint32_t y = (j & d) ? 0u : TOPB[myslot * TB + j + d];
+              if (active && !(j & d)) TOPB[myslot * TB + j] ^= y;
+            }
+            lds_order();
+          }
+        }
+        lds_order();
+        continue;
+      }
       uint32_t sw = 0u;                       // blocks of <= 32 bits: transformed word
       if (odd) {
         if (Lam <= 32) {
@@ -94,14 +137,24 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
         }
       }
       const int R = Lam > G ? (Lam >> lgG) : 1;
-      uint32_t* dst = A + myslot * N + (Lam - 1);
-      const uint32_t* src = A + myslot * N + (2 * Lam - 1);
+      uint32_t* dst = A + myslot * S + (Lam - 1);
+      const uint32_t* src = A + myslot * S + (2 * Lam - 1);
       for (int r = 0; r < R; ++r) {
         const int e = r * G + myj;
         const bool ok = active && e < Lam;
         const int ee = ok ? e : 0;
         uint32_t a, b;
-        if (s + 1 == LOGN) {
+        if (SPLIT && s + 2 == LOGN) {  // inputs from the top stage
+          if (i < H) {
+            a = TOPF[ee];
+            b = TOPF[ee + Lam];
+          } else {
+            const uint32_t ba = TOPB[myslot * TB + (ee >> 5)] >> (ee & 31);
+            const uint32_t bb = TOPB[myslot * TB + ((ee + Lam) >> 5)] >> ((ee + Lam) & 31);
+            a = TR::g(TR::load(root, ee), TR::load(root, ee + H), ba & 1u);
+            b = TR::g(TR::load(root, ee + Lam), TR::load(root, ee + Lam + H), bb & 1u);
+          }
+        } else if (s + 1 == LOGN) {
           a = TR::load(root, ee);
           b = TR::load(root, ee + Lam);
         } else {
@@ -120,7 +173,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       lds_order();
     }
     // ---- leaf decision for every entry ------------------------------------------------
-    const uint32_t a0 = lane < n ? A[phys * N] : 0u;
+    const uint32_t a0 = lane < n ? A[phys * S] : 0u;
     const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
     if constexpr (STATS) n_it += (uint32_t)n;
     if (!info) {
@@ -177,8 +230,10 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       const int k = __builtin_ctzll(todo);
       todo &= todo - 1ull;
       const uint32_t from = readlane(pslot, k), to = readlane(nslot, k);
-      for (int w = keep_from + lane; w < N - 1; w += kWave) A[to * N + w] = A[from * N + w];
+      for (int w = keep_from + lane; w < S - 1; w += kWave) A[to * S + w] = A[from * S + w];
       for (int w = lane; w < W; w += kWave) U[to * W + w] = U[from * W + w];
+      if (i >= H)
+        for (int w = lane; w < TB; w += kWave) TOPB[to * TB + w] = TOPB[from * TB + w];
     }
     lds_order();
     // bit i of every surviving entry

@@ -46,6 +46,7 @@ CASES = [
     (128, 64, 16, 8, 1.5), (256, 128, 16, 8, 1.5), (256, 200, 16, 4, 2.5),
     (512, 256, 16, 8, 1.5), (1024, 512, 16, 8, 1.5), (1024, 853, 16, 1, 2.5),
     (1024, 512, 16, 2, 1.0), (2048, 1024, 16, 4, 1.5), (2048, 1707, 16, 2, 3.0),
+    (2048, 1024, 16, 8, 1.5), (4, 2, 0, 8, 0.0),
 ]
 
 
