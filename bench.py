@@ -93,12 +93,18 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the decoder's sources with comments and blank lines removed, so that a record
+    of counters stays valid through comment edits and only a change of code voids it."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

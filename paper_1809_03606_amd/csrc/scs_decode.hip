@@ -7,18 +7,19 @@
 // their decided bits; a path switch recomputes the tree).
 //
 // Mapping (one wavefront of 64 lanes decodes one frame):
-//   * alpha tree in VGPRs: stage lambda (Lambda = 2^lambda values) puts value e in lane
-//     e mod 64 of register e / 64, so for Lambda >= 64 the f/g operands of a value sit in
-//     the same lane; for Lambda <= 32 the partner value is lane e xor Lambda and comes
-//     through DPP / ds_swizzle / ds_bpermute.  The channel LLRs are stage n.
-//   * bit vectors (decided bits, partial sums) are one VGPR: lane w holds bits
-//     32w..32w+31.  The partial sums are kept "in place" (the N-bit beta array the paper
-//     adapts for FSSCS-RM in Section 4): after PL decided bits, each complete aligned
-//     block of the PL-prefix holds its own beta.
-//   * the stack: slot s is lane s (D <= 64), holding the path metric, a packed key,
-//     the length and an incremental CRC-16 register; the decided bits of slot s live in
-//     LDS row s.  Best / worst path = wave-wide min / max reductions (DPP), free slots and
-//     pruning = ballots.
+//   * alpha tree in LDS: stage lambda (Lambda = 2^lambda values) at word offset
+//     Lambda - 1.  Stages with Lambda >= 64 are computed 64 values per instruction (value
+//     e in lane e mod 64); stages with Lambda <= 32 run in one register with the partner
+//     value from lane e xor Lambda (DPP / ds_swizzle / ds_bpermute).  The channel LLRs (stage
+//     n) are read from the input.
+//   * bit vectors (the decided bits of the path in the tree) are one VGPR: lane w holds
+//     bits 32w..32w+31.  The partial sums a g-node needs are the transform of its left
+//     sibling's decided bits, computed when the g-node is evaluated.
+//   * the stack: slot s is lane s (D <= 64), holding one 64-bit key (path metric, then
+//     N - PL and the creation number); the decided bits of slot s are word w in entry s
+//     of lane w's private array.  Best / worst path = wave-wide min / max reductions
+//     (DPP), free slots and pruning = ballots; the CRC is checked on a complete path from
+//     a byte table of syndrome shares.
 //   * a switch recomputes only the stages whose node differs between the path held in
 //     the tree and the new path (lowest common ancestor of the two leaves, and the first
 //     bit where their decisions differ); the values are identical to the paper's
