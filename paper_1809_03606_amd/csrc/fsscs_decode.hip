@@ -30,6 +30,11 @@ namespace {
 
 constexpr int kNodeR0 = 0, kNodeR1 = 1, kNodeRep = 2, kNodeSpc = 3;
 
+// A value the compiler cannot prove wave-uniform (read back from a small array) that is.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
 // Plain sum of two non-negative metric terms (the node sums; no saturation inside a sum).
 __device__ __forceinline__ uint32_t term_add(TrF32, uint32_t a, uint32_t b) {
   return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
@@ -124,10 +129,16 @@ __device__ __forceinline__ uint32_t node_alpha(int top, int lam, int i, uint32_t
 
 // Lane-wise sum with halving distance over lanes < n (n a power of two <= 64); lane 0
 // holds the result.
-template <class TR>
+// Each step's distance is a compile-time constant so the exchange is a DPP or swizzle
+// move; n is wave-uniform, so the skipped steps are scalar branches.
+template <class TR, int H = 32>
 __device__ __forceinline__ uint32_t lane_halving_sum(uint32_t w, int n) {
-  for (int h = n >> 1; h >= 1; h >>= 1) w = term_add(TR(), w, xor_lane_rt(w, h));
-  return readlane(w, 0);
+  if constexpr (H >= 1) {
+    if (n > H) w = term_add(TR(), w, xor_lane<H>(w));
+    return lane_halving_sum<TR, H / 2>(w, n);
+  } else {
+    return readlane(w, 0);
+  }
 }
 
 // Node sums of Section 2.2.4: s0 = sum of HD(alpha)|alpha|, s1 = sum of (1 - HD(alpha))|alpha|,
@@ -290,6 +301,9 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       pk = make_key(mh, ml);
       cont = pk == cand;
     }
+    // the key is wave-uniform; saying so keeps the extension in scalar control flow
+    pk = make_key((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pk >> 32)),
+                  (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pk));
     vmask &= ~(1ull << p);
     if (max_slot == p) maxk = kNone;
     cand = kNone;
@@ -317,7 +331,9 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     }
 
     // ---- the node at position i ---------------------------------------------------
-    const uint32_t nd = code.nodes[i];
+    // one aligned word through the scalar cache (i is wave-uniform); the table is padded
+    const uint32_t nw = reinterpret_cast<const uint32_t*>(code.nodes)[i >> 2];
+    const uint32_t nd = (nw >> (8 * (i & 3))) & 0xffu;
     const int lam = (int)(nd & 15u), cls = (int)(nd >> 4);
     const int Lam = 1 << lam;
     if constexpr (STATS) {
@@ -448,11 +464,11 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
         if (cls == kNodeR0) {
           x = 0u;
         } else if (cls == kNodeRep) {
-          x = kflip[c] ? (1u << (Lam - 1)) : 0u;
+          x = uniform(kflip[c]) ? (1u << (Lam - 1)) : 0u;
         } else {
           x = hdw;
           for (int k = 0; k < 4; ++k)
-            if (kflip[c] & (1u << k)) x ^= subsets32(m[k]);
+            if (uniform(kflip[c]) & (1u << k)) x ^= subsets32(m[k]);
         }
         const uint32_t fm = (Lam == 32 ? 0xFFFFFFFFu : ((1u << Lam) - 1u)) << (i & 31);
         b.in = lane == wi;
@@ -462,11 +478,11 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
         if (cls == kNodeR0) {
           x = 0u;
         } else if (cls == kNodeRep) {
-          x = (kflip[c] && lane == wi + (Lam >> 5) - 1) ? 0x80000000u : 0u;
+          x = (uniform(kflip[c]) && lane == wi + (Lam >> 5) - 1) ? 0x80000000u : 0u;
         } else {
           x = ublk;
           for (int k = 0; k < 4; ++k)
-            if (kflip[c] & (1u << k)) {
+            if (uniform(kflip[c]) & (1u << k)) {
               const int mw = m[k] >> 5;
               x ^= (((lane - wi) & ~mw) == 0) ? subsets32(m[k]) : 0u;
             }
@@ -482,7 +498,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     next_seq += (uint32_t)nk;
     const uint32_t lo0 = key_lo(N, i + Lam, seq0);
     const NodeBlock b0 = cand_block(0);
-    const uint64_t k0 = make_key(kpm[0], lo0);
+    const uint64_t k0 = make_key(uniform(kpm[0]), lo0);
     prow[b0.in ? p : kMaxD] = b0.word;
     s_key = (lane == p) ? k0 : s_key;
     vmask |= 1ull << p;
@@ -491,7 +507,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       max_slot = p;
     }
     for (int c = 1; c < nk; ++c) {
-      const uint64_t kc = make_key(kpm[c], lo0 + (uint32_t)c);
+      const uint64_t kc = make_key(uniform(kpm[c]), lo0 + (uint32_t)c);
       int t = -1;
       if (__builtin_popcountll(vmask) < D) {
         t = __builtin_ctzll(~vmask & dmask);

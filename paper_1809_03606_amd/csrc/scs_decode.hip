@@ -511,6 +511,15 @@ int device_table_bytes(const polar_code* code, CodeTable which, const void** out
     *out = it->second;
     return POLAR_OK;
   }
+  // the node table is read a 32-bit word at a time (wave-uniform scalar loads), so its
+  // copy is zero-padded to whole words: codes as short as N = 2 have 2 bytes of it
+  std::vector<uint8_t> padded;
+  if (which == kTabNodes && bytes % 4 != 0) {
+    padded.assign((const uint8_t*)src, (const uint8_t*)src + bytes);
+    padded.resize((bytes + 3) & ~(size_t)3, 0);
+    src = padded.data();
+    bytes = padded.size();
+  }
   void* tab = nullptr;
   if (hipMalloc(&tab, bytes) != hipSuccess) return POLAR_ENOMEM;
   if (hipMemcpy(tab, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {

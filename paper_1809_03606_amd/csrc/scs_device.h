@@ -16,7 +16,8 @@ struct CodeArgs {
   uint32_t info[64];
   uint16_t pre[64];
   const uint16_t* crc_tab;  // device copy of polar_code::crc_syn (null without a CRC)
-  const uint8_t* nodes;     // device copy of polar_code::nodes (fast simplified decoder)
+  const uint8_t* nodes;     // device copy of polar_code::nodes (fast simplified decoder),
+                            // zero-padded to a multiple of 4 bytes
 };
 
 inline CodeArgs make_args(const polar_code* c) {
