@@ -21,6 +21,8 @@
 //     transform), because the transform is linear and its own inverse.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "polarscs.h"
 #include "scs_device.h"
 #include "scs_launch.h"
@@ -175,37 +177,36 @@ __device__ __forceinline__ void node_sums(int lam, uint32_t x, uint32_t* vals, i
   s1 = lane_halving_sum<TR>(vals[h0 + lane], kWave);
 }
 
-// Position of the smallest |alpha| among the node's values, skipping positions in
-// `skip[0..nskip)`; ties go to the smaller position.
-__device__ __forceinline__ int node_argmin(int lam, const uint32_t* mag_reg, const uint32_t* vals,
-                                           const int* skip, int nskip, int lane, bool i8) {
-  (void)i8;
-  const int n = 1 << lam;
+// Position of the smallest magnitude among the node's n values (ties: the smaller
+// position); `mmin` receives that magnitude.  Up to 64 values: one per lane in `mag`,
+// lanes >= n holding ~0.  More: in LDS at vals[0, n).  The chosen position's magnitude is
+// then replaced by ~0 so that the next call finds the next one (magnitudes are below 2^31,
+// so ~0 is never chosen while a real value is left).
+__device__ __forceinline__ int node_argmin_take(int n, uint32_t& mag, uint32_t* vals, int lane,
+                                                uint32_t& mmin) {
+  if (n <= kWave) {
+    const uint32_t mb = wave_min(mag);
+    const int e = __builtin_ctzll(ballot(mag == mb));
+    if (lane == e) mag = 0xFFFFFFFFu;
+    mmin = mb;
+    return e;
+  }
   uint32_t best = 0xFFFFFFFFu;
   int bidx = 0x7FFFFFFF;
-  if (n <= kWave) {
-    if (lane < n) {
-      bool sk = false;
-      for (int k = 0; k < nskip; ++k) sk |= skip[k] == lane;
-      if (!sk) {
-        best = *mag_reg;
-        bidx = lane;
-      }
-    }
-  } else {
-    for (int e = lane; e < n; e += kWave) {
-      bool sk = false;
-      for (int k = 0; k < nskip; ++k) sk |= skip[k] == e;
-      const uint32_t m = vals[e];
-      if (!sk && m < best) {
-        best = m;
-        bidx = e;
-      }
+  for (int e = lane; e < n; e += kWave) {
+    const uint32_t m = vals[e];
+    if (m < best) {
+      best = m;
+      bidx = e;
     }
   }
   const uint32_t mb = wave_min(best);
-  const uint32_t key = best == mb ? (uint32_t)bidx : 0xFFFFFFFFu;
-  return (int)wave_min(key);
+  const int e = (int)wave_min(best == mb ? (uint32_t)bidx : 0xFFFFFFFFu);
+  lds_order();  // every lane has read its values before one of them is replaced
+  if (lane == 0) vals[e] = 0xFFFFFFFFu;
+  lds_order();
+  mmin = mb;
+  return e;
 }
 
 // Indicator of the subsets of m within a 32-bit word (row m & 31 of the transform).
@@ -394,7 +395,9 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     bool inb = false;    // lane holds one of the node's words
     if (!wide) {
       hdw = (uint32_t)ballot(lane < Lam && TR::hd(xa));
-      for (int s2 = 0; s2 < lam; ++s2) hdw ^= (hdw >> (1 << s2)) & kLowMask[s2];
+#pragma unroll
+      for (int s2 = 0; s2 < 5; ++s2)
+        if (s2 < lam) hdw ^= (hdw >> (1 << s2)) & kLowMask[s2];
     } else {
       inb = lane >= wi && lane < wi + (Lam >> 5);
       uint32_t v = 0u;
@@ -405,150 +408,135 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       }
 #pragma unroll
       for (int s2 = 0; s2 < 5; ++s2) v ^= (v >> (1 << s2)) & kLowMask[s2];
-      for (int s2 = 5; s2 < lam; ++s2) {
-        const int dw = 1 << (s2 - 5);
-        const uint32_t y = xor_lane_rt(v, dw);
+      // word-level steps: word w takes in word w + dw when bit dw of its offset is clear
+      auto word_step = [&](auto DW) {
+        constexpr int dw = decltype(DW)::value;
+        const uint32_t y = xor_lane<dw>(v);
         if (!((lane - wi) & dw)) v ^= y;
-      }
+      };
+      if (lam > 5) word_step(std::integral_constant<int, 1>());
+      if (lam > 6) word_step(std::integral_constant<int, 2>());
+      if (lam > 7) word_step(std::integral_constant<int, 4>());
+      if (lam > 8) word_step(std::integral_constant<int, 8>());
+      if (lam > 9) word_step(std::integral_constant<int, 16>());
+      if (lam > 10) word_step(std::integral_constant<int, 32>());
       ublk = v;
     }
     // parity of the hard decisions = u_0 of the node (row 0 of the transform is all ones)
     const int parity = wide ? (int)(readlane(ublk, wi) & 1u) : (int)(hdw & 1u);
 
-    // ---- candidates (Section 2.2.4) -------------------------------------------------
-    // candidate c: metric kpm[c]; for R-1 / SPC the flipped least reliable positions as a
-    // mask over m[0..3]; for REP whether it is the all-ones word
-    int nk = 0;
-    uint32_t kpm[8];
-    uint32_t kflip[8];
-    int m[4] = {0, 0, 0, 0};
+    // ---- candidates (Section 2.2.4), each pushed onto the stack as it is made -------
+    // Order of the node rules: R-0 one candidate; REP all-zero, then all-one; R-1 / SPC
+    // every flip mask f over the least reliable positions m[0..nlr) in increasing f (SPC:
+    // only masks whose flip count has the parity of the hard decisions).  Candidate c has
+    // sequence number seq0 + c; the first one takes the parent's slot.
+    const uint32_t seq0 = next_seq;
+    const uint32_t lo0 = key_lo(N, i + Lam, seq0);
+    const uint32_t fm = wide ? 0u : (Lam == 32 ? 0xFFFFFFFFu : ((1u << Lam) - 1u)) << (i & 31);
+    const bool bin = wide ? inb : lane == wi;  // the lane holds a word the node writes
+    uint32_t nc = 0u;
+    uint64_t k0 = kNone;
+    uint32_t w0 = 0u;
+    // x: the candidate's u bits of the node (a bit field from bit 0 for a node of <= 32
+    // leaves, else lane-per-word); pmc: its metric (wave-uniform)
+    auto push = [&](uint32_t pmc, uint32_t x) {
+      const uint32_t word = wide ? x : ((ucur & ~fm) | (x << (i & 31)));
+      const uint64_t kc = make_key(pmc, lo0 + nc);
+      if (nc == 0u) {
+        k0 = kc;
+        w0 = word;
+        prow[bin ? p : kMaxD] = word;
+        s_key = (lane == p) ? kc : s_key;
+        vmask |= 1ull << p;
+        if (kc > maxk) {
+          maxk = kc;
+          max_slot = p;
+        }
+      } else {
+        int t = -1;
+        if (__builtin_popcountll(vmask) < D) {
+          t = __builtin_ctzll(~vmask & dmask);
+          if (kc > maxk) {
+            maxk = kc;
+            max_slot = t;
+          }
+        } else {
+          if (maxk == kNone) {
+            const bool lv = (vmask >> lane) & 1ull;
+            const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
+            const uint32_t Mh = wave_max(xh);
+            const uint64_t tq = ballot(xh == Mh) & vmask;
+            uint32_t Ml;
+            if (__builtin_popcountll(tq) == 1) {
+              max_slot = __builtin_ctzll(tq);
+              Ml = readlane((uint32_t)s_key, max_slot);
+            } else {
+              const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
+              Ml = wave_max(xl);
+              max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
+            }
+            maxk = make_key(Mh, Ml);
+          }
+          if (kc < maxk) {
+            t = max_slot;
+            maxk = kNone;
+            if constexpr (STATS) ++n_ev;
+          } else {
+            if constexpr (STATS) ++n_dr;
+          }
+        }
+        if (t >= 0) {
+          prow[lane < W ? t : kMaxD] = bin ? word : ucur;
+          s_key = (lane == t) ? kc : s_key;
+          vmask |= 1ull << t;
+          if (kc < lb) lb = kc;
+        }
+      }
+      ++nc;
+    };
+
     if (cls == kNodeR0 || cls == kNodeRep) {
       uint32_t s0 = 0u, s1 = 0u;
       node_sums<TR>(lam, xa, vals, lane, s0, s1);
-      kpm[0] = TR::pm_add(ppm, s0);
-      kflip[0] = 0u;
-      nk = 1;
-      if (cls == kNodeRep) {
-        kpm[1] = TR::pm_add(ppm, s1);
-        kflip[1] = 1u;
-        nk = 2;
-      }
+      push(uniform(TR::pm_add(ppm, s0)), 0u);
+      if (cls == kNodeRep)  // re-encoded all-ones: a single 1 at the node's last position
+        push(uniform(TR::pm_add(ppm, s1)),
+             wide ? (lane == wi + (Lam >> 5) - 1 ? 0x80000000u : 0u) : 1u << (Lam - 1));
     } else {
       const int nlr = cls == kNodeR1 ? (lam >= 1 ? 2 : 1) : 4;
-      const uint32_t magr = TR::mag(xa);
+      uint32_t magr = lane < Lam ? TR::mag(xa) : 0xFFFFFFFFu;
       if (Lam > kWave) {  // magnitudes in place of the values (not needed again)
         for (int e = lane; e < Lam; e += kWave) vals[e] = TR::mag(vals[e]);
         lds_order();
       }
-      uint32_t mm[4] = {0u, 0u, 0u, 0u};
-      for (int k = 0; k < nlr; ++k) {
-        m[k] = node_argmin(lam, &magr, vals, m, k, lane, false);
-        mm[k] = Lam <= kWave ? readlane(magr, m[k]) : vals[m[k]];
+      // mm[k]: magnitude at the k-th least reliable position m; sub[k]: the u-domain
+      // change of flipping it (the subsets of m: word offsets within the node that are
+      // subsets of m >> 5, bits that are subsets of m & 31)
+      uint32_t mm[4] = {0u, 0u, 0u, 0u}, sub[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < nlr) {
+          const int e = node_argmin_take(Lam, magr, vals, lane, mm[k]);
+          sub[k] = subsets32(e);
+          if (wide) sub[k] = (((lane - wi) & ~(e >> 5)) == 0) ? sub[k] : 0u;
+        }
       }
+      const uint32_t xh = wide ? ublk : hdw;
       for (int f = 0; f < (1 << nlr); ++f) {
         if (cls == kNodeSpc && (__builtin_popcount((uint32_t)f) & 1) != parity) continue;
-        uint32_t pm = ppm;
-        for (int k = 0; k < nlr; ++k)
-          if (f & (1 << k)) pm = TR::pm_add(pm, mm[k]);
-        kpm[nk] = pm;
-        kflip[nk] = (uint32_t)f;
-        ++nk;
-      }
-    }
-    // u bits of candidate c: R-0 all 0; REP all 0 or (re-encoded all-ones) a 1 at the last
-    // position; R-1 / SPC u(HD) xor the subsets of every flipped position
-    auto cand_block = [&](int c) -> NodeBlock {
-      NodeBlock b;
-      if (!wide) {
-        uint32_t x;
-        if (cls == kNodeR0) {
-          x = 0u;
-        } else if (cls == kNodeRep) {
-          x = uniform(kflip[c]) ? (1u << (Lam - 1)) : 0u;
-        } else {
-          x = hdw;
-          for (int k = 0; k < 4; ++k)
-            if (uniform(kflip[c]) & (1u << k)) x ^= subsets32(m[k]);
-        }
-        const uint32_t fm = (Lam == 32 ? 0xFFFFFFFFu : ((1u << Lam) - 1u)) << (i & 31);
-        b.in = lane == wi;
-        b.word = (ucur & ~fm) | (x << (i & 31));
-      } else {
-        uint32_t x;
-        if (cls == kNodeR0) {
-          x = 0u;
-        } else if (cls == kNodeRep) {
-          x = (uniform(kflip[c]) && lane == wi + (Lam >> 5) - 1) ? 0x80000000u : 0u;
-        } else {
-          x = ublk;
-          for (int k = 0; k < 4; ++k)
-            if (uniform(kflip[c]) & (1u << k)) {
-              const int mw = m[k] >> 5;
-              x ^= (((lane - wi) & ~mw) == 0) ? subsets32(m[k]) : 0u;
-            }
-        }
-        b.in = inb;
-        b.word = x;
-      }
-      return b;
-    };
-
-    // ---- children onto the stack ----------------------------------------------------
-    const uint32_t seq0 = next_seq;
-    next_seq += (uint32_t)nk;
-    const uint32_t lo0 = key_lo(N, i + Lam, seq0);
-    const NodeBlock b0 = cand_block(0);
-    const uint64_t k0 = make_key(uniform(kpm[0]), lo0);
-    prow[b0.in ? p : kMaxD] = b0.word;
-    s_key = (lane == p) ? k0 : s_key;
-    vmask |= 1ull << p;
-    if (k0 > maxk) {
-      maxk = k0;
-      max_slot = p;
-    }
-    for (int c = 1; c < nk; ++c) {
-      const uint64_t kc = make_key(uniform(kpm[c]), lo0 + (uint32_t)c);
-      int t = -1;
-      if (__builtin_popcountll(vmask) < D) {
-        t = __builtin_ctzll(~vmask & dmask);
-        if (kc > maxk) {
-          maxk = kc;
-          max_slot = t;
-        }
-      } else {
-        if (maxk == kNone) {
-          const bool lv = (vmask >> lane) & 1ull;
-          const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
-          const uint32_t Mh = wave_max(xh);
-          const uint64_t tq = ballot(xh == Mh) & vmask;
-          uint32_t Ml;
-          if (__builtin_popcountll(tq) == 1) {
-            max_slot = __builtin_ctzll(tq);
-            Ml = readlane((uint32_t)s_key, max_slot);
-          } else {
-            const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
-            Ml = wave_max(xl);
-            max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
+        uint32_t pm = ppm, x = xh;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (f & (1 << k)) {
+            pm = TR::pm_add(pm, mm[k]);
+            x ^= sub[k];
           }
-          maxk = make_key(Mh, Ml);
         }
-        if (kc < maxk) {
-          t = max_slot;
-          maxk = kNone;
-          if constexpr (STATS) ++n_ev;
-        } else {
-          if constexpr (STATS) ++n_dr;
-        }
-      }
-      if (t >= 0) {
-        const NodeBlock bc = cand_block(c);
-        prow[lane < W ? t : kMaxD] = bc.in ? bc.word : ucur;
-        s_key = (lane == t) ? kc : s_key;
-        vmask |= 1ull << t;
-        if (kc < lb) lb = kc;
+        push(uniform(pm), x);
       }
     }
-    ucur = b0.in ? b0.word : ucur;
+    next_seq += nc;
+    ucur = bin ? w0 : ucur;
     lds_order();
 
     if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
@@ -559,7 +547,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     wl = i;
     wlam = lam;
     c_lo = seq0;
-    c_hi = seq0 + (uint32_t)nk;
+    c_hi = seq0 + nc;
     cand = k0;
     cand_slot = p;
   }
