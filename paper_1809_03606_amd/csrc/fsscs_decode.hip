@@ -522,17 +522,31 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
         }
       }
       const uint32_t xh = wide ? ublk : hdw;
-      for (int f = 0; f < (1 << nlr); ++f) {
-        if (cls == kNodeSpc && (__builtin_popcount((uint32_t)f) & 1) != parity) continue;
-        uint32_t pm = ppm, x = xh;
+      // every flip mask at once: lane f forms candidate f's metric (the same additions in
+      // the same order) and, for a node of <= 32 leaves, its bit field
+      uint32_t pmv = ppm, xv = xh;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (f & (1 << k)) {
-            pm = TR::pm_add(pm, mm[k]);
-            x ^= sub[k];
-          }
+      for (int k = 0; k < 4; ++k) {
+        if ((lane >> k) & 1) {
+          pmv = TR::pm_add(pmv, mm[k]);
+          xv ^= sub[k];
         }
-        push(uniform(pm), x);
+      }
+      uint64_t fset = ballot(lane < (1 << nlr) &&
+                             (cls != kNodeSpc || (__builtin_popcount((uint32_t)lane) & 1) == parity));
+      while (fset) {
+        const int f = __builtin_ctzll(fset);
+        fset &= fset - 1ull;
+        uint32_t x;
+        if (!wide) {
+          x = readlane(xv, f);
+        } else {
+          x = xh;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (f & (1 << k)) x ^= sub[k];
+        }
+        push(readlane(pmv, f), x);
       }
     }
     next_seq += nc;

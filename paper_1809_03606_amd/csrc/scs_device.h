@@ -53,7 +53,7 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
 // v from lane (lane xor M), M a power of two <= 32.
