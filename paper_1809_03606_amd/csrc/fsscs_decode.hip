@@ -439,10 +439,28 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     uint32_t w0 = 0u;
     // x: the candidate's u bits of the node (a bit field from bit 0 for a node of <= 32
     // leaves, else lane-per-word); pmc: its metric (wave-uniform)
-    auto push = [&](uint32_t pmc, uint32_t x) {
+    // the exact worst live key and its slot, when unknown
+    auto find_worst = [&]() {
+      const bool lv = (vmask >> lane) & 1ull;
+      const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
+      const uint32_t Mh = wave_max(xh);
+      const uint64_t tq = ballot(xh == Mh) & vmask;
+      uint32_t Ml;
+      if (__builtin_popcountll(tq) == 1) {
+        max_slot = __builtin_ctzll(tq);
+        Ml = readlane((uint32_t)s_key, max_slot);
+      } else {
+        const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
+        Ml = wave_max(xl);
+        max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
+      }
+      maxk = make_key(Mh, Ml);
+    };
+    // candidate c (generation order) with metric pmc and bits x
+    auto push = [&](uint32_t c, uint32_t pmc, uint32_t x) {
       const uint32_t word = wide ? x : ((ucur & ~fm) | (x << (i & 31)));
-      const uint64_t kc = make_key(pmc, lo0 + nc);
-      if (nc == 0u) {
+      const uint64_t kc = make_key(pmc, lo0 + c);
+      if (c == 0u) {
         k0 = kc;
         w0 = word;
         prow[bin ? p : kMaxD] = word;
@@ -461,22 +479,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
             max_slot = t;
           }
         } else {
-          if (maxk == kNone) {
-            const bool lv = (vmask >> lane) & 1ull;
-            const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
-            const uint32_t Mh = wave_max(xh);
-            const uint64_t tq = ballot(xh == Mh) & vmask;
-            uint32_t Ml;
-            if (__builtin_popcountll(tq) == 1) {
-              max_slot = __builtin_ctzll(tq);
-              Ml = readlane((uint32_t)s_key, max_slot);
-            } else {
-              const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
-              Ml = wave_max(xl);
-              max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
-            }
-            maxk = make_key(Mh, Ml);
-          }
+          if (maxk == kNone) find_worst();
           if (kc < maxk) {
             t = max_slot;
             maxk = kNone;
@@ -492,16 +495,18 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
           if (kc < lb) lb = kc;
         }
       }
-      ++nc;
     };
 
     if (cls == kNodeR0 || cls == kNodeRep) {
       uint32_t s0 = 0u, s1 = 0u;
       node_sums<TR>(lam, xa, vals, lane, s0, s1);
-      push(uniform(TR::pm_add(ppm, s0)), 0u);
-      if (cls == kNodeRep)  // re-encoded all-ones: a single 1 at the node's last position
-        push(uniform(TR::pm_add(ppm, s1)),
+      push(0u, uniform(TR::pm_add(ppm, s0)), 0u);
+      nc = 1u;
+      if (cls == kNodeRep) {  // re-encoded all-ones: a single 1 at the node's last position
+        push(1u, uniform(TR::pm_add(ppm, s1)),
              wide ? (lane == wi + (Lam >> 5) - 1 ? 0x80000000u : 0u) : 1u << (Lam - 1));
+        nc = 2u;
+      }
     } else {
       const int nlr = cls == kNodeR1 ? (lam >= 1 ? 2 : 1) : 4;
       uint32_t magr = lane < Lam ? TR::mag(xa) : 0xFFFFFFFFu;
@@ -532,21 +537,35 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
           xv ^= sub[k];
         }
       }
-      uint64_t fset = ballot(lane < (1 << nlr) &&
-                             (cls != kNodeSpc || (__builtin_popcount((uint32_t)lane) & 1) == parity));
+      const uint64_t fall = ballot(lane < (1 << nlr) &&
+                                   (cls != kNodeSpc || (__builtin_popcount((uint32_t)lane) & 1) == parity));
+      nc = (uint32_t)__builtin_popcountll(fall);
+      auto x_of = [&](int f) -> uint32_t {
+        if (!wide) return readlane(xv, f);
+        uint32_t x = xh;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (f & (1 << k)) x ^= sub[k];
+        return x;
+      };
+      const int f0 = __builtin_ctzll(fall);
+      push(0u, readlane(pmv, f0), x_of(f0));
+      uint64_t fset = fall & (fall - 1ull);
+      // A full stack stays full while the candidates arrive, and its worst key can only
+      // fall; so a candidate whose key is not below the worst key now is dropped whatever
+      // comes before it.  One comparison over the lanes settles all of those.
+      if (fset != 0ull && __builtin_popcountll(vmask) >= D) {
+        if (maxk == kNone) find_worst();
+        const uint32_t cl = (uint32_t)__builtin_popcountll(fall & ((1ull << lane) - 1ull));
+        const uint64_t keep = ballot(make_key(pmv, lo0 + cl) < maxk) & fset;
+        if constexpr (STATS) n_dr += (uint32_t)__builtin_popcountll(fset & ~keep);
+        fset = keep;
+      }
       while (fset) {
         const int f = __builtin_ctzll(fset);
         fset &= fset - 1ull;
-        uint32_t x;
-        if (!wide) {
-          x = readlane(xv, f);
-        } else {
-          x = xh;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (f & (1 << k)) x ^= sub[k];
-        }
-        push(readlane(pmv, f), x);
+        const uint32_t c = (uint32_t)__builtin_popcountll(fall & ((1ull << f) - 1ull));
+        push(c, readlane(pmv, f), x_of(f));
       }
     }
     next_seq += nc;
