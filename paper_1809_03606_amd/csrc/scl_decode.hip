@@ -26,14 +26,16 @@ namespace {
 
 // LDS words per wave of the list decoder: alpha stages below the top of L slots, bit rows
 // and top-stage partial sums of L slots, sibling scratch, the shared top stage, candidate
-// exchange, dummy words.
+// exchange, dummy words.  Per-slot arrays are padded so that consecutive slots start in
+// different banks: the G = 64 / L lanes of a slot work on consecutive words of their own
+// slot, and with unpadded power-of-two strides every slot's word e sits in the same bank.
 __host__ __device__ inline int scl_words_per_wave(int N, int L) {
   const int W = N >= 32 ? N / 32 : 1;
   const int SW = N >= 128 ? N / 64 : 1;  // words of the largest sibling block (N / 2 bits)
   const int S = N >= 4 ? N / 2 : N;      // per-slot alpha words
   const int TB = N >= 64 ? N / 64 : 1;   // top-stage partial sums
   const int H = N >= 4 ? N / 2 : 0;      // shared top stage
-  return L * S + L * W + L * SW + L * TB + H + 4 * 16 + kWave;
+  return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * (TB + 1) + H + 4 * 16 + kWave;
 }
 
 template <int LOGN, class TR, bool STATS>
@@ -55,16 +57,19 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   const int lgG = 6 - lgL;
   const int G = 1 << lgG;
   const int mypos = lane >> lgG, myj = lane & (G - 1);
+  // padded per-slot strides (see scl_words_per_wave)
+  const int SP = S + G;
+  constexpr int WP = W + 1, SWP = SW + 1, TBP = TB + 1;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
-  uint32_t* A = lds;                 // L x S: alpha of slot q at A + q S
-  uint32_t* U = A + L * S;           // L x W: decided bits of slot q
-  uint32_t* SIB = U + L * W;         // L x SW: sibling partial sums of list entry p
-  uint32_t* TOPB = SIB + L * SW;     // L x TB: partial sums of the first half, slot q
-  uint32_t* TOPF = TOPB + L * TB;    // H: the top stage before leaf N/2 (shared)
+  uint32_t* A = lds;                 // L x SP: alpha of slot q at A + q SP (S used)
+  uint32_t* U = A + L * SP;          // L x WP: decided bits of slot q (W used)
+  uint32_t* SIB = U + L * WP;        // L x SWP: sibling partial sums of list entry p
+  uint32_t* TOPB = SIB + L * SWP;    // L x TBP: partial sums of the first half, slot q
+  uint32_t* TOPF = TOPB + L * TBP;   // H: the top stage before leaf N/2 (shared)
   uint32_t* XC = TOPF + (SPLIT ? H : 0);  // 4 x 16: candidate exchange
   uint32_t* dummy = XC + 64;         // kWave words
 
-  for (int j = lane; j < L * W; j += kWave) U[j] = 0u;
+  for (int j = lane; j < L * WP; j += kWave) U[j] = 0u;
   lds_order();
 
   int n = 1;                         // list size
@@ -86,23 +91,23 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
         if (!odd) {  // leaf 0: f of the channel LLRs, once for all entries
           for (int e = lane; e < H; e += kWave) TOPF[e] = TR::f(TR::load(root, e), TR::load(root, e + H));
         } else if (H <= 32) {  // leaf N/2: the entry's first-half partial sums
-          uint32_t x = U[myslot * W];
+          uint32_t x = U[myslot * WP];
           if (H < 32) x &= (1u << H) - 1u;
           for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-          *(active && myj == 0 ? &TOPB[myslot * TB] : &dummy[lane]) = x;
+          *(active && myj == 0 ? &TOPB[myslot * TBP] : &dummy[lane]) = x;
         } else {
           const int nw = H >> 5;
           for (int j = myj; j < nw; j += G) {
-            uint32_t x = U[myslot * W + j];
+            uint32_t x = U[myslot * WP + j];
 #pragma unroll
             for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-            *(active ? &TOPB[myslot * TB + j] : &dummy[lane]) = x;
+            *(active ? &TOPB[myslot * TBP + j] : &dummy[lane]) = x;
           }
           lds_order();
           for (int d = 1; d < nw; d <<= 1) {
             for (int j = myj; j < nw; j += G) {
-              const uint32_t y = (j & d) ? 0u : TOPB[myslot * TB + j + d];
-              if (active && !(j & d)) TOPB[myslot * TB + j] ^= y;
+              const uint32_t y = (j & d) ? 0u : TOPB[myslot * TBP + j + d];
+              if (active && !(j & d)) TOPB[myslot * TBP + j] ^= y;
             }
             lds_order();
           }
@@ -113,7 +118,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       uint32_t sw = 0u;                       // blocks of <= 32 bits: transformed word
       if (odd) {
         if (Lam <= 32) {
-          uint32_t x = U[myslot * W + (base >> 5)] >> (base & 31);
+          uint32_t x = U[myslot * WP + (base >> 5)] >> (base & 31);
           if (Lam < 32) x &= (1u << Lam) - 1u;
           for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
           sw = x;
@@ -121,24 +126,24 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
           const int nw = Lam >> 5;
           // in-word transforms of the block's words, then across words, per entry
           for (int j = myj; j < nw; j += G) {
-            uint32_t x = U[myslot * W + (base >> 5) + j];
+            uint32_t x = U[myslot * WP + (base >> 5) + j];
 #pragma unroll
             for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-            *(active ? &SIB[mypos * SW + j] : &dummy[lane]) = x;
+            *(active ? &SIB[mypos * SWP + j] : &dummy[lane]) = x;
           }
           lds_order();
           for (int d = 1; d < nw; d <<= 1) {
             for (int j = myj; j < nw; j += G) {
-              const uint32_t y = (j & d) ? 0u : SIB[mypos * SW + j + d];
-              if (active && !(j & d)) SIB[mypos * SW + j] ^= y;
+              const uint32_t y = (j & d) ? 0u : SIB[mypos * SWP + j + d];
+              if (active && !(j & d)) SIB[mypos * SWP + j] ^= y;
             }
             lds_order();
           }
         }
       }
       const int R = Lam > G ? (Lam >> lgG) : 1;
-      uint32_t* dst = A + myslot * S + (Lam - 1);
-      const uint32_t* src = A + myslot * S + (2 * Lam - 1);
+      uint32_t* dst = A + myslot * SP + (Lam - 1);
+      const uint32_t* src = A + myslot * SP + (2 * Lam - 1);
       for (int r = 0; r < R; ++r) {
         const int e = r * G + myj;
         const bool ok = active && e < Lam;
@@ -149,8 +154,8 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
             a = TOPF[ee];
             b = TOPF[ee + Lam];
           } else {
-            const uint32_t ba = TOPB[myslot * TB + (ee >> 5)] >> (ee & 31);
-            const uint32_t bb = TOPB[myslot * TB + ((ee + Lam) >> 5)] >> ((ee + Lam) & 31);
+            const uint32_t ba = TOPB[myslot * TBP + (ee >> 5)] >> (ee & 31);
+            const uint32_t bb = TOPB[myslot * TBP + ((ee + Lam) >> 5)] >> ((ee + Lam) & 31);
             a = TR::g(TR::load(root, ee), TR::load(root, ee + H), ba & 1u);
             b = TR::g(TR::load(root, ee + Lam), TR::load(root, ee + Lam + H), bb & 1u);
           }
@@ -165,7 +170,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
         if (!odd) {
           v = TR::f(a, b);
         } else {
-          const uint32_t word = Lam <= 32 ? sw : SIB[mypos * SW + (ee >> 5)];
+          const uint32_t word = Lam <= 32 ? sw : SIB[mypos * SWP + (ee >> 5)];
           v = TR::g(a, b, (word >> (ee & 31)) & 1u);
         }
         *(ok ? &dst[ee] : &dummy[lane]) = v;
@@ -173,7 +178,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       lds_order();
     }
     // ---- leaf decision for every entry ------------------------------------------------
-    const uint32_t a0 = lane < n ? A[phys * S] : 0u;
+    const uint32_t a0 = lane < n ? A[phys * SP] : 0u;
     const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
     if constexpr (STATS) n_it += (uint32_t)n;
     if (!info) {
@@ -230,14 +235,14 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       const int k = __builtin_ctzll(todo);
       todo &= todo - 1ull;
       const uint32_t from = readlane(pslot, k), to = readlane(nslot, k);
-      for (int w = keep_from + lane; w < S - 1; w += kWave) A[to * S + w] = A[from * S + w];
-      for (int w = lane; w < W; w += kWave) U[to * W + w] = U[from * W + w];
+      for (int w = keep_from + lane; w < S - 1; w += kWave) A[to * SP + w] = A[from * SP + w];
+      for (int w = lane; w < W; w += kWave) U[to * WP + w] = U[from * WP + w];
       if (i >= H)
-        for (int w = lane; w < TB; w += kWave) TOPB[to * TB + w] = TOPB[from * TB + w];
+        for (int w = lane; w < TB; w += kWave) TOPB[to * TBP + w] = TOPB[from * TBP + w];
     }
     lds_order();
     // bit i of every surviving entry
-    if (lane < n2 && (pc & 1u)) atomicOr(&U[nslot * W + (i >> 5)], 1u << (i & 31));
+    if (lane < n2 && (pc & 1u)) atomicOr(&U[nslot * WP + (i >> 5)], 1u << (i & 31));
     lds_order();
     n = n2;
     pm = lane < n ? npm : 0u;
@@ -259,7 +264,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
     for (int q = 0; q < n; ++q) {
       const int p = __builtin_ctzll(ballot(lane < n && order == q));
       const uint32_t slot = readlane(phys, p);
-      const uint32_t row = lane < W ? U[slot * W + lane] : 0u;
+      const uint32_t row = lane < W ? U[slot * WP + lane] : 0u;
       if constexpr (STATS) ++n_cp;
       if (crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
         out = p;
@@ -269,7 +274,7 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
     }
   }
   const uint32_t oslot = readlane(phys, out);
-  const uint32_t orow = lane < W ? U[oslot * W + lane] : 0u;
+  const uint32_t orow = lane < W ? U[oslot * WP + lane] : 0u;
   if (lane < W) {
     uint32_t iw = infow;
     int k = code.pre[lane];
