@@ -32,10 +32,13 @@ namespace {
 __host__ __device__ inline int scl_words_per_wave(int N, int L) {
   const int W = N >= 32 ? N / 32 : 1;
   const int SW = N >= 128 ? N / 64 : 1;  // words of the largest sibling block (N / 2 bits)
-  const int S = N >= 4 ? N / 2 : N;      // per-slot alpha words
-  const int TB = N >= 64 ? N / 64 : 1;   // top-stage partial sums
-  const int H = N >= 4 ? N / 2 : 0;      // shared top stage
-  return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * (TB + 1) + H + 4 * 16 + kWave;
+  const int S = N >= 8 ? N / 4 : (N >= 4 ? N / 2 : N);  // per-slot alpha words
+  const int TB = N >= 64 ? N / 64 : 1;   // partial sums of the first half
+  const int QW = N >= 128 ? N / 128 : 1; // partial sums of a half's first quarter (N >= 8)
+  const int QB = N >= 8 ? L * (QW + 1) : 0;
+  const int H = N == 4 ? N / 2 : 0;      // shared top stage (N = 4 only)
+  return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * (TB + 1) + QB + H + 4 * 16 +
+         kWave;
 }
 
 template <int LOGN, class TR, bool STATS>
@@ -44,14 +47,21 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   constexpr int N = 1 << LOGN;
   constexpr int W = N >= 32 ? N / 32 : 1;
   constexpr int SW = N >= 128 ? N / 64 : 1;
-  // The top stage (N/2 values) is not kept per slot: before leaf N/2 it is f of the
-  // channel LLRs, the same for every entry (kept once); from leaf N/2 on it is g of the
-  // channel LLRs with the entry's partial sums of its first half (kept per slot, N/2 bits)
-  // and is recomputed when stage n-2 needs it (at leaves N/2 and 3N/4).
+  // The two top stages (N/2 and N/4 values) are not kept per slot (N >= 8).  Stage n-1 is
+  // f of the channel LLRs before leaf N/2 and g of them with the entry's partial sums of
+  // its first half (kept per slot, N/2 bits) from leaf N/2 on; stage n-2 is f of stage
+  // n-1 in a half's first quarter and g of it with the partial sums of that quarter (kept
+  // per slot, N/4 bits) in the second.  Both are recomputed, value by value, when stage
+  // n-3 is computed (at the leaves that are multiples of N/8), with the same operations
+  // on the same inputs as if they had been kept.  For N = 4 only the top stage is left
+  // out (kept once before leaf 2, recomputed from leaf 2 on).
   constexpr bool SPLIT = LOGN >= 2;
+  constexpr bool TWO = LOGN >= 3;
   constexpr int H = N / 2;
-  constexpr int S = SPLIT ? H : N;
+  constexpr int Q = N / 4;
+  constexpr int S = TWO ? Q : (SPLIT ? H : N);
   constexpr int TB = N >= 64 ? N / 64 : 1;
+  constexpr int QW = N >= 128 ? N / 128 : 1;
   const int lane = lane_id();
   const int lgL = 31 - __builtin_clz((uint32_t)L);
   const int lgG = 6 - lgL;
@@ -59,14 +69,15 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   const int mypos = lane >> lgG, myj = lane & (G - 1);
   // padded per-slot strides (see scl_words_per_wave)
   const int SP = S + G;
-  constexpr int WP = W + 1, SWP = SW + 1, TBP = TB + 1;
+  constexpr int WP = W + 1, SWP = SW + 1, TBP = TB + 1, QBP = QW + 1;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
   uint32_t* A = lds;                 // L x SP: alpha of slot q at A + q SP (S used)
   uint32_t* U = A + L * SP;          // L x WP: decided bits of slot q (W used)
   uint32_t* SIB = U + L * WP;        // L x SWP: sibling partial sums of list entry p
   uint32_t* TOPB = SIB + L * SWP;    // L x TBP: partial sums of the first half, slot q
-  uint32_t* TOPF = TOPB + L * TBP;   // H: the top stage before leaf N/2 (shared)
-  uint32_t* XC = TOPF + (SPLIT ? H : 0);  // 4 x 16: candidate exchange
+  uint32_t* QB = TOPB + L * TBP;     // L x QBP: partial sums of the half's first quarter
+  uint32_t* TOPF = QB + (TWO ? L * QBP : 0);      // H: the top stage before leaf 2 (N = 4)
+  uint32_t* XC = TOPF + ((SPLIT && !TWO) ? H : 0);  // 4 x 16: candidate exchange
   uint32_t* dummy = XC + 64;         // kWave words
 
   for (int j = lane; j < L * WP; j += kWave) U[j] = 0u;
@@ -79,39 +90,68 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   uint32_t n_it = 0, n_cp = 0;
   const uint32_t infow = lane < W ? code.info[lane] : 0u;
 
+  // the polar transform (partial sums) of the entry's 2^lg decided bits from bit b0 into
+  // dst[0, max(1, 2^lg / 32)): one masked word for lg <= 5, else in-word steps and then
+  // steps across words
+  auto block_sums = [&](int b0, int lg, uint32_t* dst) {
+    if (lg <= 5) {
+      uint32_t x = U[myslot * WP + (b0 >> 5)] >> (b0 & 31);
+      if (lg < 5) x &= (1u << (1 << lg)) - 1u;
+      for (int t = 0; t < lg; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+      *((mypos < n) && myj == 0 ? dst : &dummy[lane]) = x;
+    } else {
+      const int nw = 1 << (lg - 5);
+      for (int j = myj; j < nw; j += G) {
+        uint32_t x = U[myslot * WP + (b0 >> 5) + j];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+        *((mypos < n) ? &dst[j] : &dummy[lane]) = x;
+      }
+      lds_order();
+      for (int d = 1; d < nw; d <<= 1) {
+        for (int j = myj; j < nw; j += G) {
+          const uint32_t y = (j & d) ? 0u : dst[j + d];
+          if ((mypos < n) && !(j & d)) dst[j] ^= y;
+        }
+        lds_order();
+      }
+    }
+  };
+
   for (int i = 0; i < N; ++i) {
     const int top = i == 0 ? LOGN - 1 : __builtin_ctz((uint32_t)i);
     const bool active = mypos < n;
+    // value y of stage n-1 (y < N/2) and value x of stage n-2 (x < N/4) on the entry's
+    // path at leaf i, recomputed from the channel LLRs and the kept partial sums
+    auto stage1 = [&](int y) -> uint32_t {
+      const uint32_t a = TR::load(root, y), b = TR::load(root, y + H);
+      if (i < H) return TR::f(a, b);
+      return TR::g(a, b, (TOPB[myslot * TBP + (y >> 5)] >> (y & 31)) & 1u);
+    };
+    auto stage2 = [&](int x) -> uint32_t {
+      const uint32_t a = stage1(x), b = stage1(x + Q);
+      if (!((i >> (LOGN - 2)) & 1)) return TR::f(a, b);
+      return TR::g(a, b, (QB[myslot * QBP + (x >> 5)] >> (x & 31)) & 1u);
+    };
     // ---- the SC schedule for every list entry: stages top .. 0 ---------------------
     for (int s = top; s >= 0; --s) {
       const int Lam = 1 << s;
       const bool odd = (i >> s) & 1;
       const int base = ((i >> s) - 1) << s;  // left sibling block (odd nodes)
       if (SPLIT && s == LOGN - 1) {
-        if (!odd) {  // leaf 0: f of the channel LLRs, once for all entries
-          for (int e = lane; e < H; e += kWave) TOPF[e] = TR::f(TR::load(root, e), TR::load(root, e + H));
-        } else if (H <= 32) {  // leaf N/2: the entry's first-half partial sums
-          uint32_t x = U[myslot * WP];
-          if (H < 32) x &= (1u << H) - 1u;
-          for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-          *(active && myj == 0 ? &TOPB[myslot * TBP] : &dummy[lane]) = x;
-        } else {
-          const int nw = H >> 5;
-          for (int j = myj; j < nw; j += G) {
-            uint32_t x = U[myslot * WP + j];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-            *(active ? &TOPB[myslot * TBP + j] : &dummy[lane]) = x;
-          }
-          lds_order();
-          for (int d = 1; d < nw; d <<= 1) {
-            for (int j = myj; j < nw; j += G) {
-              const uint32_t y = (j & d) ? 0u : TOPB[myslot * TBP + j + d];
-              if (active && !(j & d)) TOPB[myslot * TBP + j] ^= y;
-            }
-            lds_order();
-          }
+        if (!odd) {  // leaf 0, N = 4: f of the channel LLRs, once for all entries
+          if constexpr (!TWO)
+            for (int e = lane; e < H; e += kWave)
+              TOPF[e] = TR::f(TR::load(root, e), TR::load(root, e + H));
+        } else {  // leaf N/2: the entry's first-half partial sums
+          block_sums(0, LOGN - 1, &TOPB[myslot * TBP]);
         }
+        lds_order();
+        continue;
+      }
+      if (TWO && s == LOGN - 2) {
+        if (odd)  // leaves N/4 and 3N/4: partial sums of the half's first quarter
+          block_sums(base, LOGN - 2, &QB[myslot * QBP]);
         lds_order();
         continue;
       }
@@ -149,7 +189,10 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
         const bool ok = active && e < Lam;
         const int ee = ok ? e : 0;
         uint32_t a, b;
-        if (SPLIT && s + 2 == LOGN) {  // inputs from the top stage
+        if (TWO && s + 3 == LOGN) {  // inputs: stage n-2 of the quarter, recomputed
+          a = stage2(ee);
+          b = stage2(ee + Lam);
+        } else if (SPLIT && s + 2 == LOGN) {  // inputs from the top stage (N = 4)
           if (i < H) {
             a = TOPF[ee];
             b = TOPF[ee + Lam];
@@ -239,6 +282,8 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       for (int w = lane; w < W; w += kWave) U[to * WP + w] = U[from * WP + w];
       if (i >= H)
         for (int w = lane; w < TB; w += kWave) TOPB[to * TBP + w] = TOPB[from * TBP + w];
+      if (TWO && ((i >> (LOGN - 2)) & 1))
+        for (int w = lane; w < QW; w += kWave) QB[to * QBP + w] = QB[from * QBP + w];
     }
     lds_order();
     // bit i of every surviving entry
