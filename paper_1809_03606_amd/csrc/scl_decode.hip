@@ -6,9 +6,12 @@
 // Mapping: one wavefront per frame; the L list entries (L = 1, 2, 4 or 8) share the 64
 // lanes, G = 64 / L lanes each, and every stage of the SC schedule is computed for all
 // entries at once (value e of entry p in lane p G + (e mod G)).  LDS holds, per physical
-// slot, the alpha tree (stage s at word offset 2^s - 1; the channel LLRs are read from the
-// input; the top stage is kept once while it is the same for every entry) and the decided
-// bits u (N bits); a list position points to a slot.  At an
+// slot, the alpha tree below its top kSclTop stages (stage s at word offset 2^s - 1), the
+// partial sums of the left siblings of the top stages' current nodes, and the decided
+// bits u (N bits); a list position points to a slot.  The top stages are recomputed from
+// the channel LLRs and those partial sums whenever the first kept stage is computed (at
+// leaves that are multiples of N / 2^(kSclTop + 1)), which keeps the LDS of a frame at
+// about N / 2^kSclTop words per entry.  At an
 // information leaf the 2n candidates (entry l with u = 0, then u = 1) sit in lanes; each
 // finds its rank by key (metric, candidate number) and the L best form the new list in
 // rank order.  A parent's first surviving child keeps the parent's slot; any other child
@@ -24,21 +27,56 @@
 
 namespace {
 
-// LDS words per wave of the list decoder: alpha stages below the top of L slots, bit rows
-// and top-stage partial sums of L slots, sibling scratch, the shared top stage, candidate
-// exchange, dummy words.  Per-slot arrays are padded so that consecutive slots start in
-// different banks: the G = 64 / L lanes of a slot work on consecutive words of their own
-// slot, and with unpadded power-of-two strides every slot's word e sits in the same bank.
+constexpr int kSclTop = 3;  // top stages of the tree recomputed instead of kept per slot
+
+__host__ __device__ constexpr int scl_top(int logn) { return logn - 1 < kSclTop ? logn - 1 : kSclTop; }
+
+// Words of the partial sums kept for level k (stage n - k: the transform of the current
+// node's left sibling, 2^(n-k) bits), and the per-slot words (each level padded by one) of
+// the levels before k.
+__host__ __device__ constexpr int scl_ps_words(int logn, int k) {
+  return logn - k >= 5 ? 1 << (logn - k - 5) : 1;
+}
+__host__ __device__ constexpr int scl_ps_before(int logn, int k) {
+  int o = 0;
+  for (int j = 1; j < k; ++j) o += scl_ps_words(logn, j) + 1;
+  return o;
+}
+
+// LDS words per wave of the list decoder: the kept alpha stages of L slots, bit rows of L
+// slots, sibling scratch per entry, partial sums of the recomputed stages of L slots,
+// candidate exchange, dummy words.  Per-slot arrays are padded so that consecutive slots
+// start in different banks: the G = 64 / L lanes of a slot work on consecutive words of
+// their own slot, and with unpadded power-of-two strides every slot's word e sits in the
+// same bank.
 __host__ __device__ inline int scl_words_per_wave(int N, int L) {
+  int logn = 0;
+  while ((1 << logn) < N) ++logn;
+  const int T = scl_top(logn);
   const int W = N >= 32 ? N / 32 : 1;
-  const int SW = N >= 128 ? N / 64 : 1;  // words of the largest sibling block (N / 2 bits)
-  const int S = N >= 8 ? N / 4 : (N >= 4 ? N / 2 : N);  // per-slot alpha words
-  const int TB = N >= 64 ? N / 64 : 1;   // partial sums of the first half
-  const int QW = N >= 128 ? N / 128 : 1; // partial sums of a half's first quarter (N >= 8)
-  const int QB = N >= 8 ? L * (QW + 1) : 0;
-  const int H = N == 4 ? N / 2 : 0;      // shared top stage (N = 4 only)
-  return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * (TB + 1) + QB + H + 4 * 16 +
-         kWave;
+  const int S = N >> T;                                    // kept alpha words per slot
+  const int SW = (N >> (T + 6)) > 1 ? (N >> (T + 6)) : 1;  // largest sibling block, words
+  return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * scl_ps_before(logn, T + 1) +
+         4 * 16 + kWave;
+}
+
+// Value x of stage n - K on a list entry's path at leaf i, recomputed from the channel
+// LLRs: f of the two halves of the stage above in an even node, g of them with the kept
+// partial sums of the node's left sibling (level K of slot `slot`) in an odd node.
+template <int LOGN, int K, class TR>
+__device__ __forceinline__ uint32_t stage_rec(const typename TR::In* __restrict__ root, int i,
+                                              const uint32_t* PS, int L, int slot, int x) {
+  if constexpr (K == 0) {
+    return TR::load(root, x);
+  } else {
+    constexpr int half = 1 << (LOGN - K);
+    const uint32_t a = stage_rec<LOGN, K - 1, TR>(root, i, PS, L, slot, x);
+    const uint32_t b = stage_rec<LOGN, K - 1, TR>(root, i, PS, L, slot, x + half);
+    if (!((i >> (LOGN - K)) & 1)) return TR::f(a, b);
+    const uint32_t* ps =
+        PS + L * scl_ps_before(LOGN, K) + slot * (scl_ps_words(LOGN, K) + 1);
+    return TR::g(a, b, (ps[x >> 5] >> (x & 31)) & 1u);
+  }
 }
 
 template <int LOGN, class TR, bool STATS>
@@ -46,22 +84,11 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
                                           uint32_t* lds) {
   constexpr int N = 1 << LOGN;
   constexpr int W = N >= 32 ? N / 32 : 1;
-  constexpr int SW = N >= 128 ? N / 64 : 1;
-  // The two top stages (N/2 and N/4 values) are not kept per slot (N >= 8).  Stage n-1 is
-  // f of the channel LLRs before leaf N/2 and g of them with the entry's partial sums of
-  // its first half (kept per slot, N/2 bits) from leaf N/2 on; stage n-2 is f of stage
-  // n-1 in a half's first quarter and g of it with the partial sums of that quarter (kept
-  // per slot, N/4 bits) in the second.  Both are recomputed, value by value, when stage
-  // n-3 is computed (at the leaves that are multiples of N/8), with the same operations
-  // on the same inputs as if they had been kept.  For N = 4 only the top stage is left
-  // out (kept once before leaf 2, recomputed from leaf 2 on).
-  constexpr bool SPLIT = LOGN >= 2;
-  constexpr bool TWO = LOGN >= 3;
-  constexpr int H = N / 2;
-  constexpr int Q = N / 4;
-  constexpr int S = TWO ? Q : (SPLIT ? H : N);
-  constexpr int TB = N >= 64 ? N / 64 : 1;
-  constexpr int QW = N >= 128 ? N / 128 : 1;
+  // The top T stages are not kept: stage n - T - 1 takes its inputs from stage_rec, the
+  // same operations on the same inputs as if they had been kept.
+  constexpr int T = scl_top(LOGN);
+  constexpr int S = N >> T;
+  constexpr int SW = (N >> (T + 6)) > 1 ? (N >> (T + 6)) : 1;
   const int lane = lane_id();
   const int lgL = 31 - __builtin_clz((uint32_t)L);
   const int lgG = 6 - lgL;
@@ -69,15 +96,13 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   const int mypos = lane >> lgG, myj = lane & (G - 1);
   // padded per-slot strides (see scl_words_per_wave)
   const int SP = S + G;
-  constexpr int WP = W + 1, SWP = SW + 1, TBP = TB + 1, QBP = QW + 1;
+  constexpr int WP = W + 1, SWP = SW + 1;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
   uint32_t* A = lds;                 // L x SP: alpha of slot q at A + q SP (S used)
   uint32_t* U = A + L * SP;          // L x WP: decided bits of slot q (W used)
   uint32_t* SIB = U + L * WP;        // L x SWP: sibling partial sums of list entry p
-  uint32_t* TOPB = SIB + L * SWP;    // L x TBP: partial sums of the first half, slot q
-  uint32_t* QB = TOPB + L * TBP;     // L x QBP: partial sums of the half's first quarter
-  uint32_t* TOPF = QB + (TWO ? L * QBP : 0);      // H: the top stage before leaf 2 (N = 4)
-  uint32_t* XC = TOPF + ((SPLIT && !TWO) ? H : 0);  // 4 x 16: candidate exchange
+  uint32_t* PS = SIB + L * SWP;      // levels 1 .. T: L x (words + 1) each, slot q
+  uint32_t* XC = PS + L * scl_ps_before(LOGN, T + 1);  // 4 x 16: candidate exchange
   uint32_t* dummy = XC + 64;         // kWave words
 
   for (int j = lane; j < L * WP; j += kWave) U[j] = 0u;
@@ -121,37 +146,16 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   for (int i = 0; i < N; ++i) {
     const int top = i == 0 ? LOGN - 1 : __builtin_ctz((uint32_t)i);
     const bool active = mypos < n;
-    // value y of stage n-1 (y < N/2) and value x of stage n-2 (x < N/4) on the entry's
-    // path at leaf i, recomputed from the channel LLRs and the kept partial sums
-    auto stage1 = [&](int y) -> uint32_t {
-      const uint32_t a = TR::load(root, y), b = TR::load(root, y + H);
-      if (i < H) return TR::f(a, b);
-      return TR::g(a, b, (TOPB[myslot * TBP + (y >> 5)] >> (y & 31)) & 1u);
-    };
-    auto stage2 = [&](int x) -> uint32_t {
-      const uint32_t a = stage1(x), b = stage1(x + Q);
-      if (!((i >> (LOGN - 2)) & 1)) return TR::f(a, b);
-      return TR::g(a, b, (QB[myslot * QBP + (x >> 5)] >> (x & 31)) & 1u);
-    };
     // ---- the SC schedule for every list entry: stages top .. 0 ---------------------
     for (int s = top; s >= 0; --s) {
       const int Lam = 1 << s;
       const bool odd = (i >> s) & 1;
       const int base = ((i >> s) - 1) << s;  // left sibling block (odd nodes)
-      if (SPLIT && s == LOGN - 1) {
-        if (!odd) {  // leaf 0, N = 4: f of the channel LLRs, once for all entries
-          if constexpr (!TWO)
-            for (int e = lane; e < H; e += kWave)
-              TOPF[e] = TR::f(TR::load(root, e), TR::load(root, e + H));
-        } else {  // leaf N/2: the entry's first-half partial sums
-          block_sums(0, LOGN - 1, &TOPB[myslot * TBP]);
+      if (s >= LOGN - T) {  // a recomputed stage: keep its odd node's sibling partial sums
+        if (odd) {
+          const int k = LOGN - s;
+          block_sums(base, s, PS + L * scl_ps_before(LOGN, k) + myslot * (scl_ps_words(LOGN, k) + 1));
         }
-        lds_order();
-        continue;
-      }
-      if (TWO && s == LOGN - 2) {
-        if (odd)  // leaves N/4 and 3N/4: partial sums of the half's first quarter
-          block_sums(base, LOGN - 2, &QB[myslot * QBP]);
         lds_order();
         continue;
       }
@@ -189,22 +193,9 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
         const bool ok = active && e < Lam;
         const int ee = ok ? e : 0;
         uint32_t a, b;
-        if (TWO && s + 3 == LOGN) {  // inputs: stage n-2 of the quarter, recomputed
-          a = stage2(ee);
-          b = stage2(ee + Lam);
-        } else if (SPLIT && s + 2 == LOGN) {  // inputs from the top stage (N = 4)
-          if (i < H) {
-            a = TOPF[ee];
-            b = TOPF[ee + Lam];
-          } else {
-            const uint32_t ba = TOPB[myslot * TBP + (ee >> 5)] >> (ee & 31);
-            const uint32_t bb = TOPB[myslot * TBP + ((ee + Lam) >> 5)] >> ((ee + Lam) & 31);
-            a = TR::g(TR::load(root, ee), TR::load(root, ee + H), ba & 1u);
-            b = TR::g(TR::load(root, ee + Lam), TR::load(root, ee + Lam + H), bb & 1u);
-          }
-        } else if (s + 1 == LOGN) {
-          a = TR::load(root, ee);
-          b = TR::load(root, ee + Lam);
+        if (s + T + 1 == LOGN) {  // inputs: the recomputed stage above (T = 0: the LLRs)
+          a = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee);
+          b = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee + Lam);
         } else {
           a = src[ee];
           b = src[ee + Lam];
@@ -280,10 +271,16 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
       const uint32_t from = readlane(pslot, k), to = readlane(nslot, k);
       for (int w = keep_from + lane; w < S - 1; w += kWave) A[to * SP + w] = A[from * SP + w];
       for (int w = lane; w < W; w += kWave) U[to * WP + w] = U[from * WP + w];
-      if (i >= H)
-        for (int w = lane; w < TB; w += kWave) TOPB[to * TBP + w] = TOPB[from * TBP + w];
-      if (TWO && ((i >> (LOGN - 2)) & 1))
-        for (int w = lane; w < QW; w += kWave) QB[to * QBP + w] = QB[from * QBP + w];
+      // partial sums of the recomputed stages whose current node is odd (the others are
+      // rewritten before they are read)
+#pragma unroll
+      for (int k = 1; k <= T; ++k) {
+        if ((i >> (LOGN - k)) & 1) {
+          const int nw = scl_ps_words(LOGN, k);
+          uint32_t* ps = PS + L * scl_ps_before(LOGN, k);
+          for (int w = lane; w < nw; w += kWave) ps[to * (nw + 1) + w] = ps[from * (nw + 1) + w];
+        }
+      }
     }
     lds_order();
     // bit i of every surviving entry
