@@ -27,7 +27,7 @@
 
 namespace {
 
-constexpr int kSclTop = 3;  // top stages of the tree recomputed instead of kept per slot
+constexpr int kSclTop = 4;  // top stages of the tree recomputed instead of kept per slot
 
 __host__ __device__ constexpr int scl_top(int logn) { return logn - 1 < kSclTop ? logn - 1 : kSclTop; }
 
