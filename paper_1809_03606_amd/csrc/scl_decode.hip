@@ -20,6 +20,8 @@
 // sibling's decided bits (scratch words per entry for blocks of 64 bits and more).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "polarscs.h"
 #include "scs_device.h"
 #include "scs_launch.h"
@@ -58,6 +60,15 @@ __host__ __device__ inline int scl_words_per_wave(int N, int L) {
   const int SW = (N >> (T + 6)) > 1 ? (N >> (T + 6)) : 1;  // largest sibling block, words
   return L * (S + kWave / L) + L * (W + 1) + L * (SW + 1) + L * scl_ps_before(logn, T + 1) +
          4 * 16 + kWave;
+}
+
+// f(integral_constant<int, s>) for s = S, S - 1, ..., 0 while s <= top.
+template <int S, class F>
+__device__ __forceinline__ void for_stages_desc(int top, F&& f) {
+  if constexpr (S >= 0) {
+    if (S <= top) f(std::integral_constant<int, S>());
+    for_stages_desc<S - 1>(top, f);
+  }
 }
 
 // Value x of stage n - K on a list entry's path at leaf i, recomputed from the channel
@@ -147,70 +158,77 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
     const int top = i == 0 ? LOGN - 1 : __builtin_ctz((uint32_t)i);
     const bool active = mypos < n;
     // ---- the SC schedule for every list entry: stages top .. 0 ---------------------
-    for (int s = top; s >= 0; --s) {
-      const int Lam = 1 << s;
+    // one instance of the body per stage, so that each stage's sizes are constants
+    for_stages_desc<LOGN - 1>(top, [&](auto SC) {
+      constexpr int s = decltype(SC)::value;
+      constexpr int Lam = 1 << s;
       const bool odd = (i >> s) & 1;
       const int base = ((i >> s) - 1) << s;  // left sibling block (odd nodes)
-      if (s >= LOGN - T) {  // a recomputed stage: keep its odd node's sibling partial sums
+      if constexpr (s >= LOGN - T) {  // a recomputed stage: keep its odd node's sibling sums
         if (odd) {
-          const int k = LOGN - s;
+          constexpr int k = LOGN - s;
           block_sums(base, s, PS + L * scl_ps_before(LOGN, k) + myslot * (scl_ps_words(LOGN, k) + 1));
         }
         lds_order();
-        continue;
-      }
-      uint32_t sw = 0u;                       // blocks of <= 32 bits: transformed word
-      if (odd) {
-        if (Lam <= 32) {
-          uint32_t x = U[myslot * WP + (base >> 5)] >> (base & 31);
-          if (Lam < 32) x &= (1u << Lam) - 1u;
-          for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-          sw = x;
-        } else {
-          const int nw = Lam >> 5;
-          // in-word transforms of the block's words, then across words, per entry
-          for (int j = myj; j < nw; j += G) {
-            uint32_t x = U[myslot * WP + (base >> 5) + j];
+        return;
+      } else {
+        uint32_t sw = 0u;  // blocks of <= 32 bits: transformed word
+        if (odd) {
+          if constexpr (Lam <= 32) {
+            uint32_t x = U[myslot * WP + (base >> 5)] >> (base & 31);
+            if constexpr (Lam < 32) x &= (1u << Lam) - 1u;
 #pragma unroll
-            for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
-            *(active ? &SIB[mypos * SWP + j] : &dummy[lane]) = x;
-          }
-          lds_order();
-          for (int d = 1; d < nw; d <<= 1) {
+            for (int t = 0; t < s; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+            sw = x;
+          } else {
+            constexpr int nw = Lam >> 5;
+            // in-word transforms of the block's words, then across words, per entry
             for (int j = myj; j < nw; j += G) {
-              const uint32_t y = (j & d) ? 0u : SIB[mypos * SWP + j + d];
-              if (active && !(j & d)) SIB[mypos * SWP + j] ^= y;
+              uint32_t x = U[myslot * WP + (base >> 5) + j];
+#pragma unroll
+              for (int t = 0; t < 5; ++t) x ^= (x >> (1 << t)) & kLowMask[t];
+              *(active ? &SIB[mypos * SWP + j] : &dummy[lane]) = x;
             }
             lds_order();
+#pragma unroll
+            for (int d = 1; d < nw; d <<= 1) {
+              for (int j = myj; j < nw; j += G) {
+                const uint32_t y = (j & d) ? 0u : SIB[mypos * SWP + j + d];
+                if (active && !(j & d)) SIB[mypos * SWP + j] ^= y;
+              }
+              lds_order();
+            }
           }
         }
-      }
-      const int R = Lam > G ? (Lam >> lgG) : 1;
-      uint32_t* dst = A + myslot * SP + (Lam - 1);
-      const uint32_t* src = A + myslot * SP + (2 * Lam - 1);
-      for (int r = 0; r < R; ++r) {
-        const int e = r * G + myj;
-        const bool ok = active && e < Lam;
-        const int ee = ok ? e : 0;
-        uint32_t a, b;
-        if (s + T + 1 == LOGN) {  // inputs: the recomputed stage above (T = 0: the LLRs)
-          a = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee);
-          b = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee + Lam);
-        } else {
-          a = src[ee];
-          b = src[ee + Lam];
+        const int R = Lam > G ? (Lam >> lgG) : 1;
+        uint32_t* dst = A + myslot * SP + (Lam - 1);
+        const uint32_t* src = A + myslot * SP + (2 * Lam - 1);
+        for (int r = 0; r < R; ++r) {
+          const int e = r * G + myj;
+          const bool ok = active && e < Lam;
+          const int ee = ok ? e : 0;
+          uint32_t a, b;
+          if constexpr (s + T + 1 == LOGN) {  // inputs: the recomputed stage above (T = 0: LLRs)
+            a = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee);
+            b = stage_rec<LOGN, T, TR>(root, i, PS, L, myslot, ee + Lam);
+          } else {
+            a = src[ee];
+            b = src[ee + Lam];
+          }
+          uint32_t v;
+          if (!odd) {
+            v = TR::f(a, b);
+          } else {
+            uint32_t word;
+            if constexpr (Lam <= 32) word = sw;
+            else word = SIB[mypos * SWP + (ee >> 5)];
+            v = TR::g(a, b, (word >> (ee & 31)) & 1u);
+          }
+          *(ok ? &dst[ee] : &dummy[lane]) = v;
         }
-        uint32_t v;
-        if (!odd) {
-          v = TR::f(a, b);
-        } else {
-          const uint32_t word = Lam <= 32 ? sw : SIB[mypos * SWP + (ee >> 5)];
-          v = TR::g(a, b, (word >> (ee & 31)) & 1u);
-        }
-        *(ok ? &dst[ee] : &dummy[lane]) = v;
+        lds_order();
       }
-      lds_order();
-    }
+    });
     // ---- leaf decision for every entry ------------------------------------------------
     const uint32_t a0 = lane < n ? A[phys * SP] : 0u;
     const bool info = (readlane(infow, i >> 5) >> (i & 31)) & 1u;
