@@ -244,58 +244,63 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
     const uint32_t cpm0 = (uint32_t)__builtin_amdgcn_ds_bpermute(cl << 2, (int)pm);
     const bool chd = TR::hd(ca);
     const uint32_t cpm = (lane < nc && (cu != 0) != chd) ? TR::pm_add(cpm0, TR::mag(ca)) : cpm0;
-    // rank by (metric, candidate number)
+    // rank by (metric, candidate number); lanes past the 2 L <= 16 candidates hold the
+    // largest key, above every metric, so that they are never counted
+    const uint32_t key = lane < nc ? cpm : 0xFFFFFFFFu;
     int rank = 0;
-    for (int c = 0; c < nc; ++c) {
-      const uint32_t o = readlane(cpm, c);
-      rank += (o < cpm || (o == cpm && c < lane)) ? 1 : 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const uint32_t o = readlane(key, c);
+      rank += (o < key || (o == key && c < lane)) ? 1 : 0;
     }
     const int n2 = nc < L ? nc : L;
-    // survivors: scatter (parent, bit, metric) to their new positions
     const bool surv = lane < nc && rank < n2;
-    *(surv ? &XC[rank] : &dummy[lane]) = (uint32_t)(cl << 1 | cu);
+    // the first child of a parent (the lower new position of the two candidates) keeps the
+    // parent's slot; the two candidates of a parent are neighbouring lanes
+    const bool sib_surv = xor_lane<1>((uint32_t)surv) != 0u;
+    const int sib_rank = (int)xor_lane<1>((uint32_t)rank);
+    const bool cfirst = surv && (!sib_surv || rank < sib_rank);
+    // survivors: scatter (parent, bit, first) and the metric to their new positions
+    *(surv ? &XC[rank] : &dummy[lane]) = (uint32_t)(cl << 1 | cu) | (cfirst ? 0x100u : 0u);
     *(surv ? &XC[16 + rank] : &dummy[lane]) = cpm;
+    // slots that stay in use: those of the parents with a surviving child
+    const uint64_t sv = ballot(surv);
+    uint32_t uv = (lane < n && ((sv >> ((lane & 7) * 2)) & 3ull)) ? (1u << phys) : 0u;
+    uv |= xor_lane<1>(uv);
+    uv |= xor_lane<2>(uv);
+    uv |= xor_lane<4>(uv);
+    const uint32_t used = readlane(uv, 0);
     lds_order();
-    const uint32_t pc = lane < n2 ? XC[lane] : 0u;        // new entry k: 2 parent + bit
+    const uint32_t pcx = lane < n2 ? XC[lane] : 0u;
+    const uint32_t pc = pcx & 0xFFu;                       // new entry k: 2 parent + bit
+    const bool isfirst = lane < n2 && (pcx & 0x100u);
     const uint32_t npm = lane < n2 ? XC[16 + lane] : 0u;
     const int par = (int)(pc >> 1);
     const uint32_t pslot = (uint32_t)__builtin_amdgcn_ds_bpermute(par << 2, (int)phys);
-    // the first child (lowest new position) of each parent keeps the parent's slot
-    uint64_t first = 0ull, used = 0ull;
-    for (int l = 0; l < n; ++l) {
-      const uint64_t m = ballot(lane < n2 && par == l);
-      if (m) {
-        first |= m & (~m + 1ull);
-        used |= 1ull << readlane(phys, l);
-      }
-    }
-    const bool isfirst = (first >> lane) & 1ull;
     const uint64_t others = ballot(lane < n2 && !isfirst);
-    const uint32_t freeslots = (uint32_t)(~used) & ((1u << L) - 1u);
-    // a non-first child takes the k-th free slot, k = its rank among non-first children
+    // a non-first child takes the free slots in increasing order, in order of new position
+    // (never short: n2 <= L); it copies the parent's alpha stages that later leaves read,
+    // its bit row and the kept partial sums
+    uint32_t freeslots = (uint32_t)(~used) & ((1u << L) - 1u);
     uint32_t nslot = pslot;
-    if (lane < n2 && !isfirst) {
-      int k = __builtin_popcountll(others & ((1ull << lane) - 1ull));
-      uint32_t f = freeslots;
-      for (int q = 0; q < k; ++q) f &= f - 1u;
-      nslot = f ? (uint32_t)__builtin_ctz(f) : 0u;  // never empty: n2 <= L
-    }
-    // copies for non-first children: alpha stages read later, and the bit row
     const int keep_from = (i + 1 < N) ? (2 << __builtin_ctz((uint32_t)(i + 1))) - 1 : N;
     uint64_t todo = others;
     while (todo) {
       const int k = __builtin_ctzll(todo);
       todo &= todo - 1ull;
-      const uint32_t from = readlane(pslot, k), to = readlane(nslot, k);
+      const uint32_t to = (uint32_t)__builtin_ctz(freeslots);
+      freeslots &= freeslots - 1u;
+      nslot = lane == k ? to : nslot;
+      const uint32_t from = readlane(pslot, k);
       for (int w = keep_from + lane; w < S - 1; w += kWave) A[to * SP + w] = A[from * SP + w];
       for (int w = lane; w < W; w += kWave) U[to * WP + w] = U[from * WP + w];
       // partial sums of the recomputed stages whose current node is odd (the others are
       // rewritten before they are read)
 #pragma unroll
-      for (int k = 1; k <= T; ++k) {
-        if ((i >> (LOGN - k)) & 1) {
-          const int nw = scl_ps_words(LOGN, k);
-          uint32_t* ps = PS + L * scl_ps_before(LOGN, k);
+      for (int k2 = 1; k2 <= T; ++k2) {
+        if ((i >> (LOGN - k2)) & 1) {
+          const int nw = scl_ps_words(LOGN, k2);
+          uint32_t* ps = PS + L * scl_ps_before(LOGN, k2);
           for (int w = lane; w < nw; w += kWave) ps[to * (nw + 1) + w] = ps[from * (nw + 1) + w];
         }
       }
