@@ -210,11 +210,13 @@ def write_trace_summary(trace_dir, bench_json, out_md):
              "Command (from the repository root on one MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
              "python bench.py%s --cpu-sample 0" % extra, "",
-             "Workload: N=1024, K=512 (496 payload + 16 CRC), D=32, L=8, Eb/N0 1.0/1.5/2.0/2.5/3.0 "
+             "Workload: N=1024, K=512 (496 payload + 16 CRC), %s, Eb/N0 1.0/1.5/2.0/2.5/3.0 "
              "dB, %d frames per point, launch shape %s.  Decoder launches: one counter launch "
              "per point (stats variant), %d warmup and %d timed steps of one launch per point.  "
              "The CPU-oracle sample is off so that its small launches do not enter the average."
-             % (b["config"]["frames_per_point"], b["config"].get("launch_shape"), b["warmup"],
+             % (("list of L=%d" % b["config"]["L"]) if decoder.startswith("scl") else
+                ("D=%d, L=%d" % (b["config"]["D"], b["config"]["L"])),
+                b["config"]["frames_per_point"], b["config"].get("launch_shape"), b["warmup"],
                 b["steps"]), "",
              "| kernel | calls | average ms | min ms | max ms | share of GPU time |",
              "|---|---|---|---|---|---|"]
