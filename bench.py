@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
     ap.add_argument("--points", type=str, default=",".join(str(p) for p in POINTS))
     ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
-    ap.add_argument("--cpu-sample", type=int, default=40000,
-                    help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip; "
+                         "default 40000, 8000 for the list decoder, whose oracle is slower)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
                     help="lanes per frame (0: the autotuner's choice, see --tune)")
@@ -83,7 +84,10 @@ def parse():
                          "into markdown and exit; runs on the CPU")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.cpu_sample is None:
+        a.cpu_sample = 8000 if a.decoder == "scl" else 40000
+    return a
 
 
 KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
