@@ -18,7 +18,11 @@
 //     with halving distance (w[j] += w[j + h], h = 2^lambda / 2, ..., 1);
 //   * a candidate's bits are kept in the u domain: u = (hard decisions) re-encoded, and a
 //     flip at position m adds the indicator of the subsets of m (the row m of the
-//     transform), because the transform is linear and its own inverse.
+//     transform), because the transform is linear and its own inverse;
+//   * R-1 / SPC candidates are formed all at once, one flip mask per lane, and pushed in
+//     generation order; when the stack is full after the first child, one lane-wise
+//     comparison with the worst key drops every candidate that could not enter it (a full
+//     stack stays full and its worst key only falls while the node's candidates arrive).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
