@@ -689,10 +689,13 @@ def run_fixed(args):
     print(json.dumps(line))
 
 
+DEPTHS = (8, 16, 32, 64, 128, 256)
+
+
 def run_depth(args):
     """Stack depth and L: FER and throughput of SCS and FSSCS-RM on the same 10^6 noisy
-    frames of PC(1024,512)+CRC-16 at 2 dB (and 3 dB), for D in {8, 16, 32, 64} (one stack slot
-    per lane) and L in {2, 4, 8}."""
+    frames of PC(1024,512)+CRC-16 at 2 dB (and 3 dB), for D in {8, 16, 32, 64, 128, 256} and
+    L in {2, 4, 8}, with CA-SCL (L in {2, 4, 8}) on the same frames."""
     import torch
 
     from paper_1809_03606_amd import binding, channel
@@ -721,7 +724,7 @@ def run_depth(args):
         torch.cuda.synchronize()
         for dec in ("scs", "fsscs"):
             fn = binding.fsscs_decode_batch if dec == "fsscs" else binding.scs_decode_batch
-            for d in (8, 16, 32, 64):
+            for d in DEPTHS:
                 for Lp in (2, 4, 8):
                     fn(ctx.handle, code.handle, d, Lp, binding.SCS_LLR_F32, llr, B, out, st,
                        None, stream)  # warm-up
@@ -738,6 +741,22 @@ def run_depth(args):
                                  "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
                     log("depth: %s Eb/N0 %.1f D=%d L=%d FER %.5f %.0f Mbit/s" % (
                         dec, eb, d, Lp, errs / B, rows[-1]["payload_mbps"]))
+        for Lp in (2, 4, 8):
+            binding.scl_decode_batch(ctx.handle, code.handle, Lp, binding.SCS_LLR_F32, llr, B, out,
+                                     st, None, stream)  # warm-up
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            binding.scl_decode_batch(ctx.handle, code.handle, Lp, binding.SCS_LLR_F32, llr, B, out,
+                                     st, None, stream)
+            b.record(stream)
+            stream.synchronize()
+            ms = a.elapsed_time(b)
+            errs = int((out != pay).any(dim=1).sum().item())
+            rows.append({"decoder": "scl", "ebn0_db": eb, "D": None, "L": Lp, "fer": errs / B,
+                         "fer_ci95": wilson(errs, B), "launch_ms": ms,
+                         "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
+            log("depth: scl Eb/N0 %.1f L=%d FER %.5f %.0f Mbit/s" % (
+                eb, Lp, errs / B, rows[-1]["payload_mbps"]))
         del llr, pay
     ref = [r for r in rows if r["decoder"] == "scs" and r["D"] == D and r["L"] == L]
     line = {
@@ -746,7 +765,8 @@ def run_depth(args):
         "steps": 1, "warmup": 1, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
-        "config": {"workload": "depth study PC(1024,512)+CRC16, D in {8,16,32,64}, L in {2,4,8}",
+        "config": {"workload": "depth study PC(1024,512)+CRC16, D in {8,16,32,64,128,256}, "
+                               "L in {2,4,8}; CA-SCL L in {2,4,8}",
                    "frames": B},
         "rows": rows,
     }

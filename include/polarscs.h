@@ -94,8 +94,8 @@ void scs_ctx_destroy(scs_ctx* ctx);
 
 /* Lanes of a 64-lane wavefront given to one frame: 16 or 32 (several frames share a
  * wavefront and its vector instructions) or 64 (one frame per wavefront); 0 lets the
- * library choose (64; 16 and 32 fall back to 64 when their LDS state would not fit).  Results do
- * not depend on this setting.  Errors: POLAR_EINVAL for any other value. */
+ * library choose (64; 16 and 32 fall back to 64 when their LDS state would not fit or D > 64).
+ * Results do not depend on this setting.  Errors: POLAR_EINVAL for any other value. */
 int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame);
 
 /* Wavefronts per workgroup of the decoder launches: 1, 2 or 4, or 0 for the library's
@@ -132,7 +132,7 @@ typedef struct {
  *   payload_dev n_frames x (K - crc_bits) output bits, row-major.
  *   status_dev  n_frames status bytes (SCS_STATUS_*).
  *   stats_dev   NULL, or n_frames scs_stats records.
- *   D in [1, 64], L in [1, 255].
+ *   D in [1, 256] (up to 64 slots per 64-lane bank of the stack), L in [1, 255].
  * Enqueued on hip_stream of the context's device; returns before the work runs.  The
  * result of a frame depends only on that frame's LLRs and (code, D, L).  Non-finite
  * LLRs give an unspecified output but the kernel still terminates: every frame stops
@@ -145,7 +145,7 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
 /* One frame of a mixed batch. */
 typedef struct {
   int32_t code;    /* index into the codes array */
-  int32_t D;       /* stack depth, [1, 64] */
+  int32_t D;       /* stack depth, [1, 64] in mixed batches */
   int32_t L;       /* list parameter, [1, 255] */
   int32_t _pad;    /* must be 0 */
   int64_t llr_off; /* element offset of the frame's N LLRs in llr_dev */

@@ -30,6 +30,7 @@
 #include "polarscs.h"
 #include "scs_device.h"
 #include "scs_launch.h"
+#include "scs_stack.h"
 #include "scs_tree.h"
 
 namespace {
@@ -229,7 +230,7 @@ struct NodeBlock {
   bool in;
 };
 
-template <int LOGN, class TR, bool STATS>
+template <int LOGN, class TR, bool STATS, int NB>
 __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob& job,
                                             uint32_t* lds) {
   using LY = Layout<LOGN>;
@@ -239,7 +240,8 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
   const int D = job.D, L = job.L;
   const bool use_crc = code.crc != 0;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
-  uint32_t prow[kMaxD + 1];
+  constexpr int kRow = 64 * NB;  // the row entry that takes the stores of lanes that must not
+  uint32_t prow[kRow + 1];
   uint32_t* cnt32 = lds;
   uint32_t* al = cnt32 + (N + 3) / 4;
   uint32_t* dummy = al + N;
@@ -248,9 +250,8 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
   lds_order();
 
-  uint64_t s_key = make_key(0u, key_lo(N, 0, 0u));
-  uint64_t vmask = 1ull;
-  const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
+  PathStack<NB> S;
+  S.init(D, make_key(0u, key_lo(N, 0, 0u)));
   uint32_t next_seq = 1;
   uint64_t cand = kNone, lb = 0ull;
   int cand_slot = 0;
@@ -283,33 +284,18 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       pk = cand;
       cont = true;
     } else {
-      if (vmask == 0ull) {
+      if (S.empty()) {
         st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
         out = fb;
         break;
       }
-      const bool live = (vmask >> lane) & 1ull;
-      const uint32_t kh = live ? (uint32_t)(s_key >> 32) : 0xFFFFFFFFu;
-      const uint32_t mh = wave_min(kh);
-      const uint64_t tie = ballot(kh == mh) & vmask;
-      uint32_t ml;
-      if (__builtin_popcountll(tie) == 1) {
-        p = __builtin_ctzll(tie);
-        ml = readlane((uint32_t)s_key, p);
-        lb = (uint64_t)wave_min(lane != p ? kh : 0xFFFFFFFFu) << 32;
-      } else {
-        const uint32_t kl = ((tie >> lane) & 1ull) ? (uint32_t)s_key : 0xFFFFFFFFu;
-        ml = wave_min(kl);
-        p = __builtin_ctzll(ballot(kl == ml) & tie);
-        lb = make_key(mh, ml + 1u);
-      }
-      pk = make_key(mh, ml);
+      S.best(lane, p, pk, lb);
       cont = pk == cand;
     }
     // the key is wave-uniform; saying so keeps the extension in scalar control flow
     pk = make_key((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pk >> 32)),
                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pk));
-    vmask &= ~(1ull << p);
+    S.kill(p);
     if (max_slot == p) maxk = kNone;
     cand = kNone;
     const uint32_t plo = (uint32_t)pk;
@@ -444,22 +430,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     // x: the candidate's u bits of the node (a bit field from bit 0 for a node of <= 32
     // leaves, else lane-per-word); pmc: its metric (wave-uniform)
     // the exact worst live key and its slot, when unknown
-    auto find_worst = [&]() {
-      const bool lv = (vmask >> lane) & 1ull;
-      const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
-      const uint32_t Mh = wave_max(xh);
-      const uint64_t tq = ballot(xh == Mh) & vmask;
-      uint32_t Ml;
-      if (__builtin_popcountll(tq) == 1) {
-        max_slot = __builtin_ctzll(tq);
-        Ml = readlane((uint32_t)s_key, max_slot);
-      } else {
-        const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
-        Ml = wave_max(xl);
-        max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
-      }
-      maxk = make_key(Mh, Ml);
-    };
+    auto find_worst = [&]() { S.worst(lane, max_slot, maxk); };
     // candidate c (generation order) with metric pmc and bits x
     auto push = [&](uint32_t c, uint32_t pmc, uint32_t x) {
       const uint32_t word = wide ? x : ((ucur & ~fm) | (x << (i & 31)));
@@ -467,17 +438,16 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       if (c == 0u) {
         k0 = kc;
         w0 = word;
-        prow[bin ? p : kMaxD] = word;
-        s_key = (lane == p) ? kc : s_key;
-        vmask |= 1ull << p;
+        prow[bin ? p : kRow] = word;
+        S.put(p, kc, lane);
         if (kc > maxk) {
           maxk = kc;
           max_slot = p;
         }
       } else {
         int t = -1;
-        if (__builtin_popcountll(vmask) < D) {
-          t = __builtin_ctzll(~vmask & dmask);
+        if (S.count() < D) {
+          t = S.first_free();
           if (kc > maxk) {
             maxk = kc;
             max_slot = t;
@@ -493,9 +463,8 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
           }
         }
         if (t >= 0) {
-          prow[lane < W ? t : kMaxD] = bin ? word : ucur;
-          s_key = (lane == t) ? kc : s_key;
-          vmask |= 1ull << t;
+          prow[lane < W ? t : kRow] = bin ? word : ucur;
+          S.put(t, kc, lane);
           if (kc < lb) lb = kc;
         }
       }
@@ -558,7 +527,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
       // A full stack stays full while the candidates arrive, and its worst key can only
       // fall; so a candidate whose key is not below the worst key now is dropped whatever
       // comes before it.  One comparison over the lanes settles all of those.
-      if (fset != 0ull && __builtin_popcountll(vmask) >= D) {
+      if (fset != 0ull && S.count() >= D) {
         if (maxk == kNone) find_worst();
         const uint32_t cl = (uint32_t)__builtin_popcountll(fall & ((1ull << lane) - 1ull));
         const uint64_t keep = ballot(make_key(pmv, lo0 + cl) < maxk) & fset;
@@ -578,7 +547,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
 
     if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
       if constexpr (STATS) ++n_pr;
-      vmask &= ~ballot(((uint32_t)s_key >> kSeqBits) >= (uint32_t)(N - i));
+      S.prune(N, i);
       maxk = kNone;
     }
     wl = i;
@@ -612,7 +581,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
   }
 }
 
-template <int LOGN, class TR, bool STATS>
+template <int LOGN, class TR, bool STATS, int NB>
 __global__ __launch_bounds__(256) void fsscs_uniform_kernel(CodeArgs code, int D, int L,
                                                             const typename TR::In* __restrict__ llr,
                                                             int64_t n_frames,
@@ -632,29 +601,36 @@ __global__ __launch_bounds__(256) void fsscs_uniform_kernel(CodeArgs code, int D
   job.stats = STATS ? stats + frame : nullptr;
   job.D = D;
   job.L = L;
-  fsscs_frame<LOGN, TR, STATS>(code, job, lds + wave * wave_words);
+  fsscs_frame<LOGN, TR, STATS, NB>(code, job, lds + wave * wave_words);
 }
 
 template <class TR, bool STATS>
 using FsscsKernel = void (*)(CodeArgs, int, int, const typename TR::In*, int64_t, uint8_t*,
                              uint8_t*, scs_stats*, int);
 
-template <class TR, bool STATS>
-FsscsKernel<TR, STATS> fsscs_kernel_for(int logn) {
+template <class TR, bool STATS, int NB>
+FsscsKernel<TR, STATS> fsscs_kernel_for_nb(int logn) {
   switch (logn) {
-    case 1: return fsscs_uniform_kernel<1, TR, STATS>;
-    case 2: return fsscs_uniform_kernel<2, TR, STATS>;
-    case 3: return fsscs_uniform_kernel<3, TR, STATS>;
-    case 4: return fsscs_uniform_kernel<4, TR, STATS>;
-    case 5: return fsscs_uniform_kernel<5, TR, STATS>;
-    case 6: return fsscs_uniform_kernel<6, TR, STATS>;
-    case 7: return fsscs_uniform_kernel<7, TR, STATS>;
-    case 8: return fsscs_uniform_kernel<8, TR, STATS>;
-    case 9: return fsscs_uniform_kernel<9, TR, STATS>;
-    case 10: return fsscs_uniform_kernel<10, TR, STATS>;
-    case 11: return fsscs_uniform_kernel<11, TR, STATS>;
+    case 1: return fsscs_uniform_kernel<1, TR, STATS, NB>;
+    case 2: return fsscs_uniform_kernel<2, TR, STATS, NB>;
+    case 3: return fsscs_uniform_kernel<3, TR, STATS, NB>;
+    case 4: return fsscs_uniform_kernel<4, TR, STATS, NB>;
+    case 5: return fsscs_uniform_kernel<5, TR, STATS, NB>;
+    case 6: return fsscs_uniform_kernel<6, TR, STATS, NB>;
+    case 7: return fsscs_uniform_kernel<7, TR, STATS, NB>;
+    case 8: return fsscs_uniform_kernel<8, TR, STATS, NB>;
+    case 9: return fsscs_uniform_kernel<9, TR, STATS, NB>;
+    case 10: return fsscs_uniform_kernel<10, TR, STATS, NB>;
+    case 11: return fsscs_uniform_kernel<11, TR, STATS, NB>;
     default: return nullptr;
   }
+}
+
+// one bank of 64 stack slots up to D = 64, kMaxBanks banks above
+template <class TR, bool STATS>
+FsscsKernel<TR, STATS> fsscs_kernel_for(int logn, int D) {
+  return D <= 64 ? fsscs_kernel_for_nb<TR, STATS, 1>(logn)
+                 : fsscs_kernel_for_nb<TR, STATS, kMaxBanks>(logn);
 }
 
 template <class TR>
@@ -666,13 +642,13 @@ hipError_t launch_fsscs_t(const polarscs::FsscsLaunch& a) {
   const int64_t blocks = (a.n_frames + wpb - 1) / wpb;
   (void)hipGetLastError();  // drop an error left by an earlier call of another library
   if (a.stats) {
-    auto k = fsscs_kernel_for<TR, true>(a.code.logn);
+    auto k = fsscs_kernel_for<TR, true>(a.code.logn, a.D);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.D,
                        a.L, (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status,
                        a.stats, wave_words);
   } else {
-    auto k = fsscs_kernel_for<TR, false>(a.code.logn);
+    auto k = fsscs_kernel_for<TR, false>(a.code.logn, a.D);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.D,
                        a.L, (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status,

@@ -40,13 +40,14 @@
 #include "scs_device.h"
 #include "scs_launch.h"
 
+#include "scs_stack.h"
 #include "scs_tree.h"
 
 namespace {
 
 // One frame, one wavefront.  `lds` is this wave's private region of
 // lds_words_per_wave(N, D) words.
-template <int LOGN, class TR, bool STATS>
+template <int LOGN, class TR, bool STATS, int NB = 1>
 __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJob& job,
                                              uint32_t* lds) {
   using LY = Layout<LOGN>;
@@ -58,9 +59,10 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
   // decided bits of slot s: word w in prow[s] of lane w.  Every access is by the lane
   // that owns the word, so the array is private to the lane (scratch memory, cached) and
-  // needs no ordering across lanes; entry kMaxD takes the stores of lanes that must not
+  // needs no ordering across lanes; entry kRow takes the stores of lanes that must not
   // store.
-  uint32_t prow[kMaxD + 1];
+  constexpr int kRow = 64 * NB;
+  uint32_t prow[kRow + 1];
   // Every stored row is zero past its path's length (rows are written whole from a tree
   // path that is zero there, or gain a single 1 at the decided position), so a decision of
   // 0 needs no store.  The empty path's row starts at zero.
@@ -73,10 +75,9 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
   lds_order();
 
-  // stack: slot s = lane s holds one key; its length is N - (low word >> kSeqBits)
-  uint64_t s_key = make_key(0u, key_lo(N, 0, 0u));
-  uint64_t vmask = 1ull;  // the empty path in slot 0
-  const uint64_t dmask = D >= 64 ? ~0ull : ((1ull << D) - 1ull);
+  // stack: one key per slot; a path's length is N - (low word >> kSeqBits)
+  PathStack<NB> S;
+  S.init(D, make_key(0u, key_lo(N, 0, 0u)));
   uint32_t next_seq = 1;
 
   // fast path: the first child of the last extension ("candidate", kNone if none) wins
@@ -115,30 +116,15 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       pk = cand;
       cont = true;
     } else {
-      if (vmask == 0ull) {
+      if (S.empty()) {
         st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
         out = fb;
         break;
       }
-      const bool live = (vmask >> lane) & 1ull;
-      const uint32_t kh = live ? (uint32_t)(s_key >> 32) : 0xFFFFFFFFu;
-      const uint32_t mh = wave_min(kh);
-      const uint64_t tie = ballot(kh == mh) & vmask;
-      uint32_t ml;
-      if (__builtin_popcountll(tie) == 1) {
-        p = __builtin_ctzll(tie);
-        ml = readlane((uint32_t)s_key, p);
-        lb = (uint64_t)wave_min(lane != p ? kh : 0xFFFFFFFFu) << 32;
-      } else {
-        const uint32_t kl = ((tie >> lane) & 1ull) ? (uint32_t)s_key : 0xFFFFFFFFu;
-        ml = wave_min(kl);
-        p = __builtin_ctzll(ballot(kl == ml) & tie);
-        lb = make_key(mh, ml + 1u);  // the other tied keys have larger low words
-      }
-      pk = make_key(mh, ml);
+      S.best(lane, p, pk, lb);
       cont = pk == cand;
     }
-    vmask &= ~(1ull << p);
+    S.kill(p);
     if (max_slot == p) maxk = kNone;
     cand = kNone;
     const int i = N - (int)((uint32_t)pk >> kSeqBits);  // length of the best path
@@ -217,10 +203,9 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     const uint32_t bitm = 1u << (i & 31);
     if (info && h) {  // a decided 1 (a 0 is already there)
       ucur = (lane == wi) ? (ucur | bitm) : ucur;
-      prow[lane == wi ? p : kMaxD] = ucur;
+      prow[lane == wi ? p : kRow] = ucur;
     }
-    s_key = (lane == p) ? k0 : s_key;
-    vmask |= 1ull << p;
+    S.put(p, k0, lane);
     if (k0 > maxk) {  // never true while the worst key is unknown
       maxk = k0;
       max_slot = p;
@@ -230,29 +215,14 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       // the flipped child, against the decision: metric pm1, next sequence number
       const uint64_t k1 = make_key(pm1, lo0 + 1u);
       int t = -1;
-      if (__builtin_popcountll(vmask) < D) {
-        t = __builtin_ctzll(~vmask & dmask);
+      if (S.count() < D) {
+        t = S.first_free();
         if (k1 > maxk) {
           maxk = k1;
           max_slot = t;
         }
       } else {
-        if (maxk == kNone) {
-          const bool lv = (vmask >> lane) & 1ull;
-          const uint32_t xh = lv ? (uint32_t)(s_key >> 32) : 0u;
-          const uint32_t Mh = wave_max(xh);
-          const uint64_t tq = ballot(xh == Mh) & vmask;
-          uint32_t Ml;
-          if (__builtin_popcountll(tq) == 1) {
-            max_slot = __builtin_ctzll(tq);
-            Ml = readlane((uint32_t)s_key, max_slot);
-          } else {
-            const uint32_t xl = ((tq >> lane) & 1ull) ? (uint32_t)s_key : 0u;
-            Ml = wave_max(xl);
-            max_slot = __builtin_ctzll(ballot(xl == Ml) & tq);
-          }
-          maxk = make_key(Mh, Ml);
-        }
+        if (maxk == kNone) S.worst(lane, max_slot, maxk);
         if (k1 < maxk) {
           t = max_slot;
           maxk = kNone;
@@ -262,9 +232,8 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
         }
       }
       if (t >= 0) {
-        prow[lane < W ? t : kMaxD] = ucur ^ (lane == wi ? bitm : 0u);
-        s_key = (lane == t) ? k1 : s_key;
-        vmask |= 1ull << t;
+        prow[lane < W ? t : kRow] = ucur ^ (lane == wi ? bitm : 0u);
+        S.put(t, k1, lane);
         if (k1 < lb) lb = k1;
       }
     }
@@ -273,7 +242,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     // L-counter pruning: drop every path of length <= i
     if ((int)((readlane(old, 0) >> (8 * (i & 3))) & 0xFFu) + 1 == L) {
       if constexpr (STATS) ++n_pr;
-      vmask &= ~ballot(((uint32_t)s_key >> kSeqBits) >= (uint32_t)(N - i));
+      S.prune(N, i);
       maxk = kNone;
     }
     wl = i;
@@ -305,7 +274,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   }
 }
 
-template <int LOGN, class TR, bool STATS>
+template <int LOGN, class TR, bool STATS, int NB>
 __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, int L,
                                                           const typename TR::In* __restrict__ llr,
                                                           int64_t n_frames,
@@ -325,7 +294,7 @@ __global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, 
   job.stats = STATS ? stats + frame : nullptr;
   job.D = D;
   job.L = L;
-  decode_frame<LOGN, TR, STATS>(code, job, lds + wave * wave_words);
+  decode_frame<LOGN, TR, STATS, NB>(code, job, lds + wave * wave_words);
 }
 
 // ------------------------------------------------------------------------------------
@@ -442,27 +411,33 @@ template <class TR>
 using UniformKernel = void (*)(CodeArgs, int, int, const typename TR::In*, int64_t, uint8_t*,
                                uint8_t*, scs_stats*, int);
 
-template <class TR, bool STATS>
+template <class TR, bool STATS, int NB>
 UniformKernel<TR> uniform_kernel_for_t(int logn) {
   switch (logn) {
-    case 1: return scs_uniform_kernel<1, TR, STATS>;
-    case 2: return scs_uniform_kernel<2, TR, STATS>;
-    case 3: return scs_uniform_kernel<3, TR, STATS>;
-    case 4: return scs_uniform_kernel<4, TR, STATS>;
-    case 5: return scs_uniform_kernel<5, TR, STATS>;
-    case 6: return scs_uniform_kernel<6, TR, STATS>;
-    case 7: return scs_uniform_kernel<7, TR, STATS>;
-    case 8: return scs_uniform_kernel<8, TR, STATS>;
-    case 9: return scs_uniform_kernel<9, TR, STATS>;
-    case 10: return scs_uniform_kernel<10, TR, STATS>;
-    case 11: return scs_uniform_kernel<11, TR, STATS>;
+    case 1: return scs_uniform_kernel<1, TR, STATS, NB>;
+    case 2: return scs_uniform_kernel<2, TR, STATS, NB>;
+    case 3: return scs_uniform_kernel<3, TR, STATS, NB>;
+    case 4: return scs_uniform_kernel<4, TR, STATS, NB>;
+    case 5: return scs_uniform_kernel<5, TR, STATS, NB>;
+    case 6: return scs_uniform_kernel<6, TR, STATS, NB>;
+    case 7: return scs_uniform_kernel<7, TR, STATS, NB>;
+    case 8: return scs_uniform_kernel<8, TR, STATS, NB>;
+    case 9: return scs_uniform_kernel<9, TR, STATS, NB>;
+    case 10: return scs_uniform_kernel<10, TR, STATS, NB>;
+    case 11: return scs_uniform_kernel<11, TR, STATS, NB>;
   }
   return nullptr;
 }
 
+// stack banks of 64 slots for depth D
+inline int stack_banks(int D) { return D <= 64 ? 1 : kMaxBanks; }
+
 template <class TR>
-UniformKernel<TR> uniform_kernel_for(int logn, bool stats) {
-  return stats ? uniform_kernel_for_t<TR, true>(logn) : uniform_kernel_for_t<TR, false>(logn);
+UniformKernel<TR> uniform_kernel_for(int logn, bool stats, int nb) {
+  if (nb == 1)
+    return stats ? uniform_kernel_for_t<TR, true, 1>(logn) : uniform_kernel_for_t<TR, false, 1>(logn);
+  return stats ? uniform_kernel_for_t<TR, true, kMaxBanks>(logn)
+               : uniform_kernel_for_t<TR, false, kMaxBanks>(logn);
 }
 
 int waves_per_block(int N, int D) {
@@ -653,7 +628,7 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
                      uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
                      void* hip_stream) {
   if (!ctx || !code) return POLAR_EINVAL;
-  if (D < 1 || D > 64 || L < 1 || L > 255) return POLAR_EINVAL;
+  if (D < 1 || D > kMaxDepth || L < 1 || L > 255) return POLAR_EINVAL;
   if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
   if (n_frames < 0) return POLAR_EINVAL;
   if (n_frames == 0) return POLAR_OK;
@@ -699,12 +674,12 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
   clear_stale_error();
   if (llr_dtype == SCS_LLR_F32) {
-    auto k = uniform_kernel_for<TrF32>(code->logn, stats_dev != nullptr);
+    auto k = uniform_kernel_for<TrF32>(code->logn, stats_dev != nullptr, stack_banks(D));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
                        (const float*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
                        wave_words);
   } else {
-    auto k = uniform_kernel_for<TrI8>(code->logn, stats_dev != nullptr);
+    auto k = uniform_kernel_for<TrI8>(code->logn, stats_dev != nullptr, stack_banks(D));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, args, (int)D, (int)L,
                        (const int8_t*)llr_dev, n_frames, payload_dev, status_dev, stats_dev,
                        wave_words);
@@ -723,7 +698,7 @@ int fsscs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t 
                        uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,
                        void* hip_stream) {
   if (!ctx || !code) return POLAR_EINVAL;
-  if (D < 1 || D > 64 || L < 1 || L > 255) return POLAR_EINVAL;
+  if (D < 1 || D > kMaxDepth || L < 1 || L > 255) return POLAR_EINVAL;
   if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
   if (n_frames < 0) return POLAR_EINVAL;
   if (n_frames == 0) return POLAR_OK;

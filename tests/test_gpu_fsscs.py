@@ -59,6 +59,26 @@ def test_fsscs_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
     _run(cuda, N, K, crc, D, L, eb, B, seed=41 + N, dtype="i8")
 
 
+# stacks deeper than one 64-slot bank (D up to 256), filled by low Eb/N0 and large L
+DEEP = [
+    (16, 8, 0, 256, 255, 0.0), (64, 32, 0, 65, 8, 1.0), (128, 64, 16, 100, 8, 1.0),
+    (256, 128, 16, 128, 16, 1.0), (512, 256, 16, 200, 16, 1.0), (1024, 512, 16, 256, 8, 1.0),
+    (1024, 512, 16, 129, 8, 2.0), (1024, 853, 16, 192, 64, 2.0), (2048, 1024, 16, 256, 8, 1.5),
+]
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", DEEP)
+def test_fsscs_deep_stack_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=71 + N + D)
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", DEEP[1::2])
+def test_fsscs_deep_stack_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=81 + N + D, dtype="i8")
+
+
 @pytest.mark.parametrize("eb", [1.0, 2.0, 3.0])
 def test_fsscs_n1024_crc16_points(cuda, eb):
     """PC(1024,512)+CRC-16, D = 32, L = 8 at three Eb/N0 points, 400 frames each."""

@@ -53,6 +53,28 @@ SMALL = [
 ]
 
 
+# Stacks deeper than one 64-slot bank (D up to 256): low Eb/N0 and large L so that the
+# stack fills past 64 slots, evicts and drops; D just above a bank boundary; a tiny code
+# under a huge stack.  A request for 16 or 32 lanes per frame runs 64 lanes for these.
+DEEP = [
+    (16, 8, 0, 256, 255, 0.0), (64, 32, 0, 65, 8, 1.0), (128, 64, 16, 100, 8, 1.0),
+    (256, 128, 16, 128, 16, 1.0), (512, 256, 16, 200, 16, 1.0), (1024, 512, 16, 256, 8, 1.0),
+    (1024, 512, 16, 129, 8, 2.0), (1024, 853, 16, 192, 255, 2.0), (2048, 1024, 16, 256, 8, 1.5),
+]
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", DEEP)
+def test_gpu_deep_stack_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=51 + N + D)
+
+
+@pytest.mark.parametrize("N,K,crc,D,L,eb", DEEP[1::2])
+def test_gpu_deep_stack_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
+    B = 37 if N >= 1024 else 101
+    _run(cuda, N, K, crc, D, L, eb, B, seed=61 + N + D, dtype="i8", lanes=16)
+
+
 @pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("N,K,crc,D,L,eb", SMALL)
 def test_gpu_matches_oracle_f32(cuda, N, K, crc, D, L, eb, lanes):
@@ -128,7 +150,7 @@ def test_gpu_empty_batch_and_bad_arguments(cuda):
     pay = cuda.zeros((1, 32), dtype=cuda.uint8, device="cuda")
     st = cuda.zeros((1,), dtype=cuda.uint8, device="cuda")
     binding.scs_decode_batch(ctx.handle, code.handle, 8, 8, 0, x, 0, pay, st)
-    for D, L in [(0, 8), (65, 8), (8, 0), (8, 256)]:
+    for D, L in [(0, 8), (257, 8), (8, 0), (8, 256)]:
         with pytest.raises(binding.PolarError) as e:
             binding.scs_decode_batch(ctx.handle, code.handle, D, L, 0, pay, 1, pay, st)
         assert e.value.code == binding.POLAR_EINVAL
