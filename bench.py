@@ -154,9 +154,9 @@ def _counter_kib(folder: str, counter: str, kernel: str, exclude: str = "\0"):
 def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_000_000):
     """HBM bytes per decoder launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each
     scaled by what the same counter reads for a device copy of COPY_BYTES."""
-    # the timed launch only: the counter launch (", true>" variant) also writes statistics
-    dec_f = _counter_kib(fetch_dir, "FETCH_SIZE", DECODER, ", true>")
-    dec_w = _counter_kib(write_dir, "WRITE_SIZE", DECODER, ", true>")
+    # the timed launch only: the counter launch (the ", true" variant) also writes statistics
+    dec_f = _counter_kib(fetch_dir, "FETCH_SIZE", DECODER, ", true")
+    dec_w = _counter_kib(write_dir, "WRITE_SIZE", DECODER, ", true")
     cp_f = max(_counter_kib(cfetch_dir, "FETCH_SIZE", "copyBuffer"))  # the device copy
     cp_w = max(_counter_kib(cwrite_dir, "WRITE_SIZE", "copyBuffer"))
     ff = COPY_BYTES / (cp_f * 1024.0)
@@ -228,7 +228,7 @@ def write_trace_summary(trace_dir, bench_json, out_md):
         lines.append("| %s | %d | %.3f | %.3f | %.3f | %.2f%% |" % (
             k, len(v), np.mean(v), min(v), max(v), 100.0 * sum(v) / total))
     dec = [d for k, v in per.items() if k.startswith(decoder) for d in v]
-    timed = [d for k, v in per.items() if k.startswith(decoder) and ", true>" not in k for d in v]
+    timed = [d for k, v in per.items() if k.startswith(decoder) and ", true" not in k for d in v]
     lines += ["", "Decoder mean over all %d launches (points mixed): %.1f ms.  Without the counter "
               "launches (%d warmup + timed launches): %.1f ms.  bench.py's HIP-event mean over its "
               "timed launches: %.1f ms (`roofline.mean_launch_ms`); bench value %.1f Mbit/s." % (

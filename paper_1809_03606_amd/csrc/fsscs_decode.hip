@@ -626,11 +626,12 @@ FsscsKernel<TR, STATS> fsscs_kernel_for_nb(int logn) {
   }
 }
 
-// one bank of 64 stack slots up to D = 64, kMaxBanks banks above
+// banks of 64 stack slots: one up to D = 64, two up to 128, kMaxBanks above
 template <class TR, bool STATS>
 FsscsKernel<TR, STATS> fsscs_kernel_for(int logn, int D) {
-  return D <= 64 ? fsscs_kernel_for_nb<TR, STATS, 1>(logn)
-                 : fsscs_kernel_for_nb<TR, STATS, kMaxBanks>(logn);
+  if (D <= 64) return fsscs_kernel_for_nb<TR, STATS, 1>(logn);
+  if (D <= 128) return fsscs_kernel_for_nb<TR, STATS, 2>(logn);
+  return fsscs_kernel_for_nb<TR, STATS, kMaxBanks>(logn);
 }
 
 template <class TR>

@@ -429,13 +429,15 @@ UniformKernel<TR> uniform_kernel_for_t(int logn) {
   return nullptr;
 }
 
-// stack banks of 64 slots for depth D
-inline int stack_banks(int D) { return D <= 64 ? 1 : kMaxBanks; }
+// stack banks of 64 slots for depth D: 1, 2 or kMaxBanks
+inline int stack_banks(int D) { return D <= 64 ? 1 : (D <= 128 ? 2 : kMaxBanks); }
 
 template <class TR>
 UniformKernel<TR> uniform_kernel_for(int logn, bool stats, int nb) {
   if (nb == 1)
     return stats ? uniform_kernel_for_t<TR, true, 1>(logn) : uniform_kernel_for_t<TR, false, 1>(logn);
+  if (nb == 2)
+    return stats ? uniform_kernel_for_t<TR, true, 2>(logn) : uniform_kernel_for_t<TR, false, 2>(logn);
   return stats ? uniform_kernel_for_t<TR, true, kMaxBanks>(logn)
                : uniform_kernel_for_t<TR, false, kMaxBanks>(logn);
 }
