@@ -91,7 +91,7 @@ def parse():
 
 
 KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
-                  "paper_1809_03606_amd/csrc/scs_tree.h",
+                  "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h",
                   "paper_1809_03606_amd/csrc/scs_rows.hip")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
 
