@@ -570,31 +570,32 @@ int scs_ctx_create(int device, scs_ctx** out) {
   if (!c) return POLAR_ENOMEM;
   c->device = device;
   int dev0 = 0;
-  hipGetDevice(&dev0);
+  (void)hipGetDevice(&dev0);
   if (hipSetDevice(device) != hipSuccess ||
       hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipMalloc(&c->d_counter, sizeof(uint32_t)) != hipSuccess ||
       hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
-    hipFree(c->d_counter);
+    (void)hipFree(c->d_counter);
     delete c;
-    hipSetDevice(dev0);
+    (void)hipSetDevice(dev0);
     return POLAR_EDEVICE;
   }
-  hipSetDevice(dev0);
+  (void)hipSetDevice(dev0);
   *out = c;
   return POLAR_OK;
 }
 
 void scs_ctx_destroy(scs_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
-  hipFree(ctx->d_codes);
-  hipFree(ctx->d_frames);
-  hipFree(ctx->d_order);
-  hipFree(ctx->d_counter);
-  if (ctx->h_stage) hipHostFree(ctx->h_stage);
-  if (ctx->staged) hipEventDestroy(ctx->staged);
+  // teardown: errors here cannot be acted on
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->d_codes);
+  (void)hipFree(ctx->d_frames);
+  (void)hipFree(ctx->d_order);
+  (void)hipFree(ctx->d_counter);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   delete ctx;
 }
 
@@ -815,14 +816,14 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
   if (nc > ctx->cap_codes || nf > ctx->cap_frames) {
     if (hipDeviceSynchronize() != hipSuccess) return POLAR_EDEVICE;
     if (nc > ctx->cap_codes) {
-      hipFree(ctx->d_codes);
+      (void)hipFree(ctx->d_codes);  // the device is idle (synchronized above)
       ctx->d_codes = nullptr;
       if (hipMalloc(&ctx->d_codes, nc * sizeof(CodeArgs)) != hipSuccess) return POLAR_ENOMEM;
       ctx->cap_codes = nc;
     }
     if (nf > ctx->cap_frames) {
-      hipFree(ctx->d_frames);
-      hipFree(ctx->d_order);
+      (void)hipFree(ctx->d_frames);
+      (void)hipFree(ctx->d_order);
       ctx->d_frames = nullptr;
       ctx->d_order = nullptr;
       if (hipMalloc(&ctx->d_frames, nf * sizeof(scs_frame)) != hipSuccess ||
@@ -834,7 +835,7 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
   const size_t bytes = nc * sizeof(CodeArgs) + nf * sizeof(scs_frame) + nf * sizeof(int32_t);
   if (hipEventSynchronize(ctx->staged) != hipSuccess) return POLAR_EDEVICE;  // staging free
   if (bytes > ctx->cap_stage) {
-    if (ctx->h_stage) hipHostFree(ctx->h_stage);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     ctx->h_stage = nullptr;
     if (hipHostMalloc((void**)&ctx->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
       return POLAR_ENOMEM;
