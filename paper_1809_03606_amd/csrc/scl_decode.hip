@@ -90,8 +90,8 @@ __device__ __forceinline__ uint32_t stage_rec(const typename TR::In* __restrict_
   }
 }
 
-template <int LOGN, class TR, bool STATS>
-__device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& job, int L,
+template <int LOGN, class TR, bool STATS, int L>
+__device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& job,
                                           uint32_t* lds) {
   constexpr int N = 1 << LOGN;
   constexpr int W = N >= 32 ? N / 32 : 1;
@@ -101,12 +101,15 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   constexpr int S = N >> T;
   constexpr int SW = (N >> (T + 6)) > 1 ? (N >> (T + 6)) : 1;
   const int lane = lane_id();
-  const int lgL = 31 - __builtin_clz((uint32_t)L);
-  const int lgG = 6 - lgL;
-  const int G = 1 << lgG;
+  // the list size is a compile-time constant: G lanes per entry, loop trip counts and slot
+  // strides are constants
+  constexpr int lgL = L == 1 ? 0 : (L == 2 ? 1 : (L == 4 ? 2 : 3));
+  static_assert((1 << lgL) == L, "L is 1, 2, 4 or 8");
+  constexpr int lgG = 6 - lgL;
+  constexpr int G = 1 << lgG;
   const int mypos = lane >> lgG, myj = lane & (G - 1);
   // padded per-slot strides (see scl_words_per_wave)
-  const int SP = S + G;
+  constexpr int SP = S + G;
   constexpr int WP = W + 1, SWP = SW + 1;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
   uint32_t* A = lds;                 // L x SP: alpha of slot q at A + q SP (S used)
@@ -363,8 +366,8 @@ __device__ __forceinline__ void scl_frame(const CodeArgs& code, const FrameJob& 
   }
 }
 
-template <int LOGN, class TR, bool STATS>
-__global__ __launch_bounds__(256) void scl_uniform_kernel(CodeArgs code, int L,
+template <int LOGN, class TR, bool STATS, int L>
+__global__ __launch_bounds__(256) void scl_uniform_kernel(CodeArgs code, int /*L: the template's*/,
                                                           const typename TR::In* __restrict__ llr,
                                                           int64_t n_frames,
                                                           uint8_t* __restrict__ payload,
@@ -383,27 +386,38 @@ __global__ __launch_bounds__(256) void scl_uniform_kernel(CodeArgs code, int L,
   job.stats = STATS ? stats + frame : nullptr;
   job.D = 0;
   job.L = L;
-  scl_frame<LOGN, TR, STATS>(code, job, L, lds + wave * wave_words);
+  scl_frame<LOGN, TR, STATS, L>(code, job, lds + wave * wave_words);
 }
 
 template <class TR, bool STATS>
 using SclKernel = void (*)(CodeArgs, int, const typename TR::In*, int64_t, uint8_t*, uint8_t*,
                            scs_stats*, int);
 
-template <class TR, bool STATS>
-SclKernel<TR, STATS> scl_kernel_for(int logn) {
+template <class TR, bool STATS, int L>
+SclKernel<TR, STATS> scl_kernel_for_l(int logn) {
   switch (logn) {
-    case 1: return scl_uniform_kernel<1, TR, STATS>;
-    case 2: return scl_uniform_kernel<2, TR, STATS>;
-    case 3: return scl_uniform_kernel<3, TR, STATS>;
-    case 4: return scl_uniform_kernel<4, TR, STATS>;
-    case 5: return scl_uniform_kernel<5, TR, STATS>;
-    case 6: return scl_uniform_kernel<6, TR, STATS>;
-    case 7: return scl_uniform_kernel<7, TR, STATS>;
-    case 8: return scl_uniform_kernel<8, TR, STATS>;
-    case 9: return scl_uniform_kernel<9, TR, STATS>;
-    case 10: return scl_uniform_kernel<10, TR, STATS>;
-    case 11: return scl_uniform_kernel<11, TR, STATS>;
+    case 1: return scl_uniform_kernel<1, TR, STATS, L>;
+    case 2: return scl_uniform_kernel<2, TR, STATS, L>;
+    case 3: return scl_uniform_kernel<3, TR, STATS, L>;
+    case 4: return scl_uniform_kernel<4, TR, STATS, L>;
+    case 5: return scl_uniform_kernel<5, TR, STATS, L>;
+    case 6: return scl_uniform_kernel<6, TR, STATS, L>;
+    case 7: return scl_uniform_kernel<7, TR, STATS, L>;
+    case 8: return scl_uniform_kernel<8, TR, STATS, L>;
+    case 9: return scl_uniform_kernel<9, TR, STATS, L>;
+    case 10: return scl_uniform_kernel<10, TR, STATS, L>;
+    case 11: return scl_uniform_kernel<11, TR, STATS, L>;
+    default: return nullptr;
+  }
+}
+
+template <class TR, bool STATS>
+SclKernel<TR, STATS> scl_kernel_for(int logn, int L) {
+  switch (L) {
+    case 1: return scl_kernel_for_l<TR, STATS, 1>(logn);
+    case 2: return scl_kernel_for_l<TR, STATS, 2>(logn);
+    case 4: return scl_kernel_for_l<TR, STATS, 4>(logn);
+    case 8: return scl_kernel_for_l<TR, STATS, 8>(logn);
     default: return nullptr;
   }
 }
@@ -416,13 +430,13 @@ hipError_t launch_scl_t(const polarscs::SclLaunch& a) {
   const int64_t blocks = (a.n_frames + wpb - 1) / wpb;
   (void)hipGetLastError();  // drop an error left by an earlier call of another library
   if (a.stats) {
-    auto k = scl_kernel_for<TR, true>(a.code.logn);
+    auto k = scl_kernel_for<TR, true>(a.code.logn, a.L);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.L,
                        (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status, a.stats,
                        wave_words);
   } else {
-    auto k = scl_kernel_for<TR, false>(a.code.logn);
+    auto k = scl_kernel_for<TR, false>(a.code.logn, a.L);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, a.code, a.L,
                        (const typename TR::In*)a.llr, a.n_frames, a.payload, a.status, a.stats,
