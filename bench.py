@@ -79,6 +79,9 @@ def parse():
                     help="write the HBM traffic record from four rocprofv3 --pmc output folders "
                          "(decoder FETCH_SIZE, decoder WRITE_SIZE, 1 GiB copy FETCH_SIZE and "
                          "WRITE_SIZE) and exit; runs on the CPU")
+    ap.add_argument("--counters-record", nargs=2, metavar=("SQ_DIR", "BENCH_JSON"),
+                    help="write the SCS instruction-count record from a rocprofv3 --pmc SQ_* folder "
+                         "and that run's JSON line, and exit; runs on the CPU")
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "BENCH_JSON", "OUT_MD"),
                     help="summarise a rocprofv3 --kernel-trace --stats folder of a bench run "
                          "into markdown and exit; runs on the CPU")
@@ -94,6 +97,8 @@ KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_
                   "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h",
                   "paper_1809_03606_amd/csrc/scs_rows.hip")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
+COUNTERS_RECORD = os.path.join(ROOT, "profiles", "decoder_counters_n1024.json")
+CU_CYCLES_PER_S = 256 * 2.4e9  # MI355X: 256 CUs at 2.4 GHz
 
 
 def kernel_source_hash() -> str:
@@ -123,6 +128,59 @@ def measured_traffic(frames_per_launch: int):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec["hbm_bytes_per_frame"] * frames_per_launch
+
+
+def issue_bound(per_point, frames):
+    """The SCS kernel against its binding resource, scalar instruction issue (one per CU per
+    cycle): recorded scalar instructions per path extension (SQ_INSTS_SALU of the 2 dB point)
+    over the CU-cycles per extension of this run at 2 dB.  None without a record taken on the
+    current kernel sources or without a 2 dB point."""
+    try:
+        with open(COUNTERS_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or 2.0 not in per_point:
+        return None
+    p = per_point[2.0]
+    if not frames or not p.get("mean_iterations"):
+        return None
+    cycles = p["launch_ms"] * 1e-3 * CU_CYCLES_PER_S / (frames * p["mean_iterations"])
+    salu = rec["per_extension"]["SQ_INSTS_SALU"]
+    return {"bound": "scalar issue (1 instruction per CU per cycle)",
+            "scalar_insts_per_extension": salu,
+            "vector_insts_per_extension": rec["per_extension"]["SQ_INSTS_VALU"],
+            "cu_cycles_per_extension": cycles, "frac": salu / cycles, "at_ebn0_db": 2.0}
+
+
+def write_counters_record(sq_dir, bench_json):
+    """Instructions per path extension of the timed SCS launch from a rocprofv3 --pmc SQ_*
+    folder of `bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 --cpu-sample 0`."""
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    agg = {}
+    for r in _csv_rows(sq_dir, "counter_collection.csv"):
+        name = r["Kernel_Name"]
+        if DECODER in name and ", true" not in name:
+            agg[r["Counter_Name"]] = agg.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    p = b["per_point"]["2.0"]
+    ext = p["mean_iterations"] * b["config"]["frames_per_point"]
+    rec = {
+        "kernel": DECODER + "<10,f32> (64 lanes per frame, one stack bank)",
+        "kernel_source_hash": kernel_source_hash(),
+        "workload": "PC(1024,512)+CRC16, D=32, L=8, Eb/N0 2.0 dB, %d frames"
+                    % b["config"]["frames_per_point"],
+        "command": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
+                   "SQ_INSTS_SMEM SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_BRANCH --output-format csv "
+                   "-d <dir> -o run -- python bench.py --frames 100000 --points 2.0 --steps 1 "
+                   "--warmup 0 --cpu-sample 0",
+        "extensions": ext,
+        "totals": agg,
+        "per_extension": {k: v / ext for k, v in agg.items()},
+    }
+    with open(COUNTERS_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"counters_record": COUNTERS_RECORD, "per_extension": rec["per_extension"]}))
 
 
 COPY_BYTES = 1 << 30
@@ -259,6 +317,9 @@ def main():
         return
     if args.traffic_record:
         write_traffic_record(*args.traffic_record)
+        return
+    if args.counters_record:
+        write_counters_record(*args.counters_record)
         return
     if args.trace_summary:
         write_trace_summary(*args.trace_summary)
@@ -417,13 +478,17 @@ def main():
     mean_launch_s = float(all_ms.mean()) * 1e-3
     achieved = ops_per_launch / mean_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    # the counter records were taken on the binary32 SCS kernel at 64 lanes per frame
+    recorded = (not fast and not scl and args.dtype == "f32"
+                and launch_shape["lanes_per_frame"] in (0, 64) and D <= 64)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                "frac": achieved / peak, "traffic": None if fast else measured_traffic(B),
+                "frac": achieved / peak, "traffic": measured_traffic(B) if recorded else None,
                 "kernel": ("fsscs_uniform_kernel" if fast else "scl_uniform_kernel" if scl else
                            "scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
                            else "scs_rows_kernel<%d>" % launch_shape["lanes_per_frame"])
                           + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
-                "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch}
+                "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch,
+                "issue": issue_bound(per_point, B) if recorded else None}
 
     # -- CPU oracle on a bounded sample of the same frames -----------------------------
     cpu = None

@@ -1,0 +1,81 @@
+"""Host logic of bench.py's counter records: the source hash that keys them, the refusal of
+a record taken on other sources, the scalar-issue figure and the counters-record writer."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+@pytest.fixture
+def sources(tmp_path, monkeypatch):
+    a = tmp_path / "a.hip"
+    a.write_text("int f() {\n  return 1;  // one\n}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ("a.hip",))
+    return a
+
+
+def test_source_hash_ignores_comments_and_blank_lines(sources):
+    h0 = bench.kernel_source_hash()
+    sources.write_text("// header\nint f() {\n\n  return 1;  // another comment\n}\n")
+    assert bench.kernel_source_hash() == h0
+    sources.write_text("int f() {\n  return 2;\n}\n")
+    assert bench.kernel_source_hash() != h0
+
+
+def test_records_are_refused_for_other_sources(sources, tmp_path, monkeypatch):
+    traffic = tmp_path / "traffic.json"
+    counters = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(traffic))
+    monkeypatch.setattr(bench, "COUNTERS_RECORD", str(counters))
+    assert bench.measured_traffic(10) is None  # no record
+    traffic.write_text(json.dumps({"kernel_source_hash": bench.kernel_source_hash(),
+                                   "hbm_bytes_per_frame": 100.0}))
+    assert bench.measured_traffic(10) == 1000.0
+    counters.write_text(json.dumps({"kernel_source_hash": bench.kernel_source_hash(),
+                                    "per_extension": {"SQ_INSTS_SALU": 90.0,
+                                                      "SQ_INSTS_VALU": 70.0}}))
+    # 1000 frames x 2000 extensions in t ms: cycles per extension = t e-3 x CU_CYCLES_PER_S / 2e6
+    t_ms = 2e6 * 100.0 / bench.CU_CYCLES_PER_S * 1e3  # 100 CU-cycles per extension
+    per_point = {2.0: {"mean_iterations": 2000.0, "launch_ms": t_ms}}
+    got = bench.issue_bound(per_point, 1000)
+    assert got["cu_cycles_per_extension"] == pytest.approx(100.0)
+    assert got["frac"] == pytest.approx(0.9)
+    assert bench.issue_bound({3.0: per_point[2.0]}, 1000) is None  # no 2 dB point
+    sources.write_text("int f() {\n  return 3;\n}\n")  # the code changed since the records
+    assert bench.measured_traffic(10) is None
+    assert bench.issue_bound(per_point, 1000) is None
+
+
+def test_counters_record_excludes_the_statistics_launch(sources, tmp_path, monkeypatch):
+    sq = tmp_path / "sq" / "run"
+    sq.mkdir(parents=True)
+    rows = []
+    for kernel, salu in [("void scs_uniform_kernel<10, TrF32, false, 1>(x)", 9.0e6),
+                         ("void scs_uniform_kernel<10, TrF32, true, 1>(x)", 5.0e9),
+                         ("void other_kernel(x)", 7.0e9)]:
+        rows.append({"Kernel_Name": kernel, "Counter_Name": "SQ_INSTS_SALU",
+                     "Counter_Value": salu, "Dispatch_Id": len(rows)})
+        rows.append({"Kernel_Name": kernel, "Counter_Name": "SQ_INSTS_VALU",
+                     "Counter_Value": salu / 2, "Dispatch_Id": len(rows)})
+    with open(sq / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    line = {"config": {"frames_per_point": 1000}, "per_point": {"2.0": {"mean_iterations": 100.0}}}
+    bj = tmp_path / "bench.json"
+    bj.write_text("log line\n" + json.dumps(line) + "\n")
+    out = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "COUNTERS_RECORD", str(out))
+    bench.write_counters_record(str(tmp_path / "sq"), str(bj))
+    rec = json.loads(out.read_text())
+    assert rec["kernel_source_hash"] == bench.kernel_source_hash()
+    assert rec["per_extension"]["SQ_INSTS_SALU"] == pytest.approx(90.0)
+    assert rec["per_extension"]["SQ_INSTS_VALU"] == pytest.approx(45.0)
