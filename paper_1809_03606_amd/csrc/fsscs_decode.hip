@@ -5,9 +5,9 @@
 // candidate of the node's list rule (Section 2.2.4) on the stack, with one alpha tree per
 // frame recomputed on a path switch (the reduced-memory scheme of Section 3.3).
 //
-// Mapping: as the SCS kernel (one wavefront per frame, stack slot s = lane s holding a
-// 64-bit key, the decided bits u of slot s in lane-private memory, L counters and the
-// alpha tree in LDS).  Per extension:
+// Mapping: as the SCS kernel (one wavefront per frame, the banked stack of scs_stack.h
+// with one 64-bit key per slot, the decided bits u of slot s in lane-private memory, L
+// counters and the alpha tree in LDS).  Per extension:
 //   * the alpha tree is computed from the first stale stage down to the node's stage
 //     lambda (not to the leaves);
 //   * the node's 2^lambda LLRs sit one per lane (up to 64) or in LDS, 64 per row;

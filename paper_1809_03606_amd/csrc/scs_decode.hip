@@ -15,7 +15,8 @@
 //   * bit vectors (the decided bits of the path in the tree) are one VGPR: lane w holds
 //     bits 32w..32w+31.  The partial sums a g-node needs are the transform of its left
 //     sibling's decided bits, computed when the g-node is evaluated.
-//   * the stack: slot s is lane s (D <= 64), holding one 64-bit key (path metric, then
+//   * the stack (scs_stack.h): slot s is lane s mod 64 of bank s / 64 (one bank for
+//     D <= 64, up to four for D <= 256), holding one 64-bit key (path metric, then
 //     N - PL and the creation number); the decided bits of slot s are word w in entry s
 //     of lane w's private array.  Best / worst path = wave-wide min / max reductions
 //     (DPP), free slots and pruning = ballots; the CRC is checked on a complete path from
