@@ -41,8 +41,8 @@ enum {
   SCS_STATUS_OK = 1,        /* output path passed the CRC (or there is no CRC) */
   SCS_STATUS_FALLBACK = 2,  /* every complete path failed the CRC; the first one is output */
   SCS_STATUS_EXHAUSTED = 4  /* decoding stopped because the stack emptied */
-  /* a status byte of 0: the iteration bound (L N + L extensions) was reached, which only
-   * non-finite LLRs can cause; the payload is then unspecified */
+  /* a status byte of 0: the safeguard bound of L N + L extensions was reached (the L
+   * counters keep every search below it, so it is not expected); payload unspecified */
 };
 
 /* LLR element types. */
