@@ -715,6 +715,8 @@ def run_fixed(args):
 
     def decode(x, n):
         dt = binding.SCS_LLR_F32 if x.dtype == torch.float32 else binding.SCS_LLR_I8
+        # x was just written on the default stream: the decoder's stream waits for it
+        stream.wait_stream(torch.cuda.current_stream())
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         binding.scs_decode_batch(ctx.handle, code.handle, D, L, dt, x, n, out, st, None, stream)
