@@ -87,6 +87,7 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
     code.encode_device(pay, cw)
     llr = channel.device_llr(torch, gen, cw, ebn0_db, code.rate, dtype)
     del cw
+    torch.cuda.synchronize()  # the LLRs are written on the default stream, decoded on another
     out = torch.empty((frames, code.payload_bits), dtype=torch.uint8, device=dev)
     st = torch.empty((frames,), dtype=torch.uint8, device=dev)
     ctx = binding.ScsContext(0)
