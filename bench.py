@@ -762,7 +762,7 @@ DEPTHS = (8, 16, 32, 64, 128, 256)
 def run_depth(args):
     """Stack depth and L: FER and throughput of SCS and FSSCS-RM on the same 10^6 noisy
     frames of PC(1024,512)+CRC-16 at 2 dB (and 3 dB), for D in {8, 16, 32, 64, 128, 256} and
-    L in {2, 4, 8}, with CA-SCL (L in {2, 4, 8}) on the same frames."""
+    L in {2, 4, 8}, with CA-SCL (L in {1, 2, 4, 8}) on the same frames."""
     import torch
 
     from paper_1809_03606_amd import binding, channel
@@ -808,7 +808,7 @@ def run_depth(args):
                                  "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
                     log("depth: %s Eb/N0 %.1f D=%d L=%d FER %.5f %.0f Mbit/s" % (
                         dec, eb, d, Lp, errs / B, rows[-1]["payload_mbps"]))
-        for Lp in (2, 4, 8):
+        for Lp in (1, 2, 4, 8):
             binding.scl_decode_batch(ctx.handle, code.handle, Lp, binding.SCS_LLR_F32, llr, B, out,
                                      st, None, stream)  # warm-up
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -833,7 +833,7 @@ def run_depth(args):
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
         "config": {"workload": "depth study PC(1024,512)+CRC16, D in {8,16,32,64,128,256}, "
-                               "L in {2,4,8}; CA-SCL L in {2,4,8}",
+                               "L in {2,4,8}; CA-SCL L in {1,2,4,8}",
                    "frames": B},
         "rows": rows,
     }

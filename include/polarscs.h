@@ -212,9 +212,11 @@ int fsscs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t 
  * CRC is the output (status SCS_STATUS_OK); if none passes, the first path with status
  * SCS_STATUS_FALLBACK.  Without a CRC the best path, status OK.  Buffers and statistics as
  * scs_decode_batch (iterations = path extensions, L per leaf once the list is full;
- * completions = CRC checks; the other counters 0).  Errors: POLAR_EINVAL for another L or a
- * bad argument; POLAR_EUNSUPPORTED when the state of one frame would exceed 64 KB of LDS
- * (it does not for N <= 2048, L <= 8). */
+ * completions = CRC checks; the other counters 0).  At L <= 4 a wavefront decodes 8 / L
+ * frames together; each frame's outputs do not depend on the other frames of the batch.
+ * Errors: POLAR_EINVAL for another L or a bad argument; POLAR_EUNSUPPORTED when the LDS
+ * state of one wavefront (eight list entries) would exceed 64 KB (it does not for
+ * N <= 2048). */
 int scl_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t L, int32_t llr_dtype,
                      const void* llr_dev, int64_t n_frames, uint8_t* payload_dev,
                      uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream);

@@ -62,3 +62,19 @@ def test_scl_matches_oracle_i8(cuda, N, K, crc, L, eb):
 
 def test_scl_n1024_l8_2db(cuda):
     got, pay = _run(cuda, 1024, 512, 16, 8, 2.0, 400, seed=9)
+
+
+# Several frames share a wavefront at L <= 4 (8 list entries per wavefront): batches of one
+# frame, a partly filled last wavefront, exactly full wavefronts and one frame more.
+PACKED = [(L, B) for L, F in ((1, 8), (2, 4), (4, 2))
+          for B in sorted({1, F - 1, F, F + 1, 3 * F + 1})]
+
+
+@pytest.mark.parametrize("L,B", PACKED)
+def test_scl_packed_frames_f32(cuda, L, B):
+    _run(cuda, 256, 128, 16, L, 1.5, B, seed=70 + 10 * L + B)
+
+
+@pytest.mark.parametrize("L,B", PACKED[::2])
+def test_scl_packed_frames_i8(cuda, L, B):
+    _run(cuda, 128, 64, 0, L, 1.0, B, seed=90 + 10 * L + B, dtype="i8")
