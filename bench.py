@@ -26,6 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N, K, CRC, D, L = 1024, 512, 16, 32, 8
+HEADLINE_DL = (D, L)
+
+
+def sweep_config(d, l):
+    """Another stack depth / L for the sweep workload (the other workloads keep theirs)."""
+    global D, L
+    if not (1 <= d <= 256 and 1 <= l <= 255):
+        raise SystemExit("bench.py: D must be in [1, 256] and L in [1, 255]")
+    D, L = d, l
 POINTS = (1.0, 1.5, 2.0, 2.5, 3.0)
 SEED = 2
 PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 32-bit VALU lane-operations per second
@@ -64,6 +73,11 @@ def parse():
                     help="scs: successive-cancellation stack decoding (the headline); fsscs: "
                          "fast simplified stack decoding (FSSCS-RM); scl: CA-SCL with a list "
                          "of L paths; all on the same frames")
+    ap.add_argument("--D", type=int, default=D,
+                    help="stack depth of the sweep (1..256; the headline is D = 32)")
+    ap.add_argument("--L", type=int, default=L,
+                    help="L of the sweep: the stack decoders' path-length counter (1..255) or "
+                         "the list size of CA-SCL (1, 2, 4, 8); the headline is L = 8")
     ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
                     help="launch-shape autotuner: use the cached choice or tune once (auto), "
                          "always re-tune (force), or use the library's defaults (off)")
@@ -268,6 +282,11 @@ def write_trace_summary(trace_dir, bench_json, out_md):
              "CA-SCL" if decoder.startswith("scl") else "SCS")
     extra = (" --decoder fsscs" if decoder.startswith("fsscs") else
              " --decoder scl" if decoder.startswith("scl") else "")
+    cfg = b["config"]
+    if not decoder.startswith("scl") and cfg["D"] != HEADLINE_DL[0]:
+        extra += " --D %d" % cfg["D"]
+    if cfg["L"] != HEADLINE_DL[1]:
+        extra += " --L %d" % cfg["L"]
     lines = ["# Kernel trace: %s decoder, PC(1024,512)+CRC-16 sweep" % title, "",
              "Command (from the repository root on one MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
@@ -336,6 +355,8 @@ def main():
             sys.exit(2)
         {"fixed": run_fixed, "depth": run_depth}[args.workload](args)
         return
+    if args.workload == "sweep" and (args.D, args.L) != (D, L):
+        sweep_config(args.D, args.L)
     if args.gpus != 1:
         print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
               "independent, see the design notes for how the batch would shard)" % args.gpus,
@@ -478,9 +499,10 @@ def main():
     mean_launch_s = float(all_ms.mean()) * 1e-3
     achieved = ops_per_launch / mean_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    # the counter records were taken on the binary32 SCS kernel at 64 lanes per frame
+    # the counter records were taken on the binary32 SCS kernel at 64 lanes per frame, on
+    # the headline configuration
     recorded = (not fast and not scl and args.dtype == "f32"
-                and launch_shape["lanes_per_frame"] in (0, 64) and D <= 64)
+                and launch_shape["lanes_per_frame"] in (0, 64) and (D, L) == HEADLINE_DL)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                 "frac": achieved / peak, "traffic": measured_traffic(B) if recorded else None,
                 "kernel": ("fsscs_uniform_kernel" if fast else "scl_uniform_kernel" if scl else
@@ -525,13 +547,18 @@ def main():
 
     line = {
         "metric": "info Mbit/s decoded (N=1024,K=512,D=32) at oracle-matched FER; p99 latency"
-                  + ("; FSSCS-RM decoder" if fast else "; CA-SCL decoder, list 8" if scl else ""),
+                  + ("; FSSCS-RM decoder" if fast else "; CA-SCL decoder, list %d" % L if scl
+                     else "")
+                  + ("; D=%d, L=%d" % (D, L) if not scl and (D, L) != HEADLINE_DL else ""),
         "value": value, "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
         "config": {"workload": ("FSSCS-RM" if fast else "CA-SCL" if scl else "SCS")
-                               + " sweep PC(1024,512)+CRC16 D=32 L=8 Eb/N0 1.0-3.0 dB",
+                               + (" sweep PC(1024,512)+CRC16 L=%d" % L if scl else
+                                  " sweep PC(1024,512)+CRC16 D=%d L=%d" % (D, L))
+                               + (" Eb/N0 1.0-3.0 dB" if points == list(POINTS) else
+                                  " Eb/N0 %s dB" % ",".join("%g" % p for p in points)),
                    "N": N, "K": K, "crc_bits": CRC, "D": D, "L": L,
                    "ebn0_db": points, "frames_per_point": B, "global_batch": B * len(points),
                    "launches_per_step": len(points), "parallelism": "single GPU",

@@ -79,3 +79,14 @@ def test_counters_record_excludes_the_statistics_launch(sources, tmp_path, monke
     assert rec["kernel_source_hash"] == bench.kernel_source_hash()
     assert rec["per_extension"]["SQ_INSTS_SALU"] == pytest.approx(90.0)
     assert rec["per_extension"]["SQ_INSTS_VALU"] == pytest.approx(45.0)
+
+
+def test_sweep_config_bounds_and_headline(monkeypatch):
+    monkeypatch.setattr(bench, "D", bench.D)
+    monkeypatch.setattr(bench, "L", bench.L)
+    assert (bench.D, bench.L) == bench.HEADLINE_DL == (32, 8)
+    for bad in ((0, 8), (257, 8), (32, 0), (32, 256)):
+        with pytest.raises(SystemExit):
+            bench.sweep_config(*bad)
+    bench.sweep_config(128, 4)
+    assert (bench.D, bench.L) == (128, 4)
