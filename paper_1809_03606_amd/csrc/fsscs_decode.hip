@@ -295,13 +295,14 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     // the key is wave-uniform; saying so keeps the extension in scalar control flow
     pk = make_key((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pk >> 32)),
                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pk));
-    S.kill(p);
+    // the slot stays live while the path is extended: its first candidate takes it over
     if (max_slot == p) maxk = kNone;
     cand = kNone;
     const uint32_t plo = (uint32_t)pk;
     const int i = N - (int)(plo >> kSeqBits);
 
     if (i == N) {
+      S.kill(p);
       if constexpr (STATS) ++n_cp;
       const uint32_t row = lane < W ? prow[p] : 0u;
       if (!use_crc || crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
@@ -439,7 +440,7 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
         k0 = kc;
         w0 = word;
         prow[bin ? p : kRow] = word;
-        S.put(p, kc, lane);
+        S.rekey(p, kc, lane);
         if (kc > maxk) {
           maxk = kc;
           max_slot = p;

@@ -125,13 +125,14 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       S.best(lane, p, pk, lb);
       cont = pk == cand;
     }
-    S.kill(p);
+    // the slot stays live while the path is extended: its first child takes it over
     if (max_slot == p) maxk = kNone;
     cand = kNone;
     const int i = N - (int)((uint32_t)pk >> kSeqBits);  // length of the best path
 
     if (i == N) {
       // a complete path: the CRC decides (Section 2.2.5)
+      S.kill(p);
       if constexpr (STATS) ++n_cp;
       const uint32_t row = lane < W ? prow[p] : 0u;
       if (!use_crc || crc_syndrome(code.crc_tab, row, lane, W, (N + 7) / 8) == 0u) {
@@ -206,7 +207,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       ucur = (lane == wi) ? (ucur | bitm) : ucur;
       prow[lane == wi ? p : kRow] = ucur;
     }
-    S.put(p, k0, lane);
+    S.rekey(p, k0, lane);
     if (k0 > maxk) {  // never true while the worst key is unknown
       maxk = k0;
       max_slot = p;

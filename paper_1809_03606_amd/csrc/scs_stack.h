@@ -217,6 +217,16 @@ struct PathStack {
     }
   }
 
+  // slot s, which holds a path, takes key k (the path is replaced by its first child)
+  __device__ __forceinline__ void rekey(int s, uint64_t k, int lane) {
+    if constexpr (NB == 1) {
+      key[0] = (lane == s) ? k : key[0];
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) key[b] = (b == (s >> 6) && lane == (s & 63)) ? k : key[b];
+    }
+  }
+
   // L-counter pruning: drop every path of length <= i
   __device__ __forceinline__ void prune(int N, int i) {
 #pragma unroll
