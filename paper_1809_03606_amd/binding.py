@@ -127,6 +127,23 @@ def _addr(x) -> int | None:
     return int(x.data_ptr())
 
 
+def _device_buffer(t, name: str, dtypes, min_elems: int, device: int | None):
+    """Check a torch tensor handed to a kernel: on the expected GPU, contiguous, of one of
+    `dtypes`, with at least `min_elems` elements (so the kernel stays inside it)."""
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a GPU tensor" % name)
+    if device is not None and t.device.index != device:
+        raise ValueError("%s is on cuda:%s, the context on cuda:%d" % (name, t.device.index, device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s; expected one of %s" % (name, t.dtype, dtypes))
+    if t.numel() < min_elems:
+        raise ValueError("%s holds %d elements; at least %d needed" % (name, t.numel(), min_elems))
+
+
 def _stream(s) -> int | None:
     if s is None:
         return None
@@ -271,7 +288,14 @@ class PolarCode:
         return cw
 
     def encode_device(self, payload_dev, codeword_dev, stream=None):
-        polar_encode_device(self.handle, payload_dev, codeword_dev, payload_dev.shape[0], stream)
+        """Encode frames x payload_bits uint8 payloads into frames x N uint8 codewords."""
+        import torch
+
+        n = payload_dev.shape[0]
+        _device_buffer(payload_dev, "payload", (torch.uint8,), n * self.payload_bits, None)
+        _device_buffer(codeword_dev, "codewords", (torch.uint8,), n * self.N,
+                       payload_dev.device.index)
+        polar_encode_device(self.handle, payload_dev, codeword_dev, n, stream)
 
     def close(self):
         if self.handle:
@@ -298,15 +322,28 @@ class ScsContext:
         scs_ctx_set_lanes(self.handle, lanes_per_frame)
         scs_ctx_set_waves_per_block(self.handle, waves_per_block)
 
+    def _frames(self, code: PolarCode, llr_dev, payload_dev, status_dev, stats_dev):
+        """Check the buffers of one batch; returns (LLR dtype code, frames)."""
+        import torch  # device buffers are torch tensors here
+
+        if llr_dev.numel() % code.N:
+            raise ValueError("LLRs hold %d values, not a multiple of N = %d" % (llr_dev.numel(),
+                                                                               code.N))
+        n = llr_dev.numel() // code.N
+        _device_buffer(llr_dev, "llr", (torch.float32, torch.int8), n * code.N, self.device)
+        if code.payload_bits > 0 or payload_dev is not None:
+            _device_buffer(payload_dev, "payload", (torch.uint8,), n * code.payload_bits,
+                           self.device)
+        _device_buffer(status_dev, "status", (torch.uint8,), n, self.device)
+        if stats_dev is not None:
+            _device_buffer(stats_dev, "stats", (torch.int32, torch.uint32), n * len(STATS_FIELDS),
+                           self.device)
+        return (SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8), n
+
     def decode(self, code: PolarCode, D: int, L: int, llr_dev, payload_dev, status_dev,
                stats_dev=None, stream=None, fast: bool = False):
         """SCS decoding of llr_dev (frames x N); fast=True: FSSCS-RM (fsscs_decode_batch)."""
-        import torch  # device buffers are torch tensors here
-
-        dtype = SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8
-        if llr_dev.dtype not in (torch.float32, torch.int8):
-            raise TypeError("LLRs must be float32 or int8")
-        n = llr_dev.numel() // code.N
+        dtype, n = self._frames(code, llr_dev, payload_dev, status_dev, stats_dev)
         fn = fsscs_decode_batch if fast else scs_decode_batch
         fn(self.handle, code.handle, D, L, dtype, llr_dev, n, payload_dev, status_dev, stats_dev,
            stream)
@@ -314,10 +351,7 @@ class ScsContext:
     def decode_list(self, code: PolarCode, L: int, llr_dev, payload_dev, status_dev,
                     stats_dev=None, stream=None):
         """CA-SCL decoding of llr_dev (frames x N) with a list of L paths."""
-        import torch
-
-        dtype = SCS_LLR_F32 if llr_dev.dtype == torch.float32 else SCS_LLR_I8
-        n = llr_dev.numel() // code.N
+        dtype, n = self._frames(code, llr_dev, payload_dev, status_dev, stats_dev)
         scl_decode_batch(self.handle, code.handle, L, dtype, llr_dev, n, payload_dev, status_dev,
                          stats_dev, stream)
 
