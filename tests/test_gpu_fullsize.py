@@ -25,7 +25,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _full(cuda, ebn0, dtype, seed, decoder="scs"):
+def _full(cuda, ebn0, dtype, seed, decoder="scs", list_size=L):
     from paper_1809_03606_amd import binding
 
     torch = cuda
@@ -54,9 +54,9 @@ def _full(cuda, ebn0, dtype, seed, decoder="scs"):
     out = torch.empty((FRAMES, kp), dtype=torch.uint8, device="cuda")
     st = torch.empty((FRAMES,), dtype=torch.uint8, device="cuda")
     ctx = binding.ScsContext(0)
-    _say("gpu: full-size %s %s batch at %.1f dB" % (decoder, dtype, ebn0))
+    _say("gpu: full-size %s %s batch at %.1f dB (list %d)" % (decoder, dtype, ebn0, list_size))
     if decoder == "scl":
-        ctx.decode_list(code, L, llr, out, st)
+        ctx.decode_list(code, list_size, llr, out, st)
     else:
         ctx.decode(code, D, L, llr, out, st, fast=decoder == "fsscs")
     torch.cuda.synchronize()
@@ -74,7 +74,7 @@ def _full(cuda, ebn0, dtype, seed, decoder="scs"):
         mode = oracle.FIX
     assert np.array_equal(h_llr.view(np.uint8), d_llr.view(np.uint8))
     if decoder == "scl":
-        rp, rs, _ = oracle.scl_decode_batch(mode, info, CRC, L, h_llr, threads=THREADS)
+        rp, rs, _ = oracle.scl_decode_batch(mode, info, CRC, list_size, h_llr, threads=THREADS)
     elif decoder == "fsscs":
         rp, rs, _ = oracle.fsscs_decode_batch(mode, info, CRC, D, L, h_llr, threads=THREADS)
     else:
@@ -97,3 +97,9 @@ def test_gpu_full_size_fixed_point_sampled_against_oracle(cuda):
 @pytest.mark.parametrize("decoder", ["fsscs", "scl"])
 def test_gpu_full_size_other_decoders_sampled_against_oracle(cuda, decoder):
     _full(cuda, 2.0, "f32", seed=40, decoder=decoder)
+
+
+@pytest.mark.parametrize("list_size", [1, 4])
+def test_gpu_full_size_packed_list_decoder_sampled_against_oracle(cuda, list_size):
+    # 8 / L frames share a wavefront; the sample falls anywhere in the packed batch
+    _full(cuda, 2.0, "f32", seed=50 + list_size, decoder="scl", list_size=list_size)
