@@ -89,6 +89,53 @@ __device__ __forceinline__ void for_stages_desc(int top, F&& f) {
   }
 }
 
+// The rank of a lane's key among the keys of its aligned group of G2 <= 16 lanes, by
+// (key, lane): the number of lanes in the group with a smaller key, or an equal key and a
+// lower lane.  Every other lane of the group is visited once through a DPP exchange inside
+// the lane's row (lane xor m for groups of up to 8, a rotation of the 16-lane row for 16);
+// the tie rule needs only whether the visited lane is the lower one, a fixed function of
+// the lane number for each exchange.
+template <int G2>
+__device__ __forceinline__ int group_rank(uint32_t key, int lane) {
+  int r = 0;
+  auto count = [&](uint32_t o, bool lower) { r += (o < key || (o == key && lower)) ? 1 : 0; };
+  if constexpr (G2 == 16) {
+    const int g = lane & 15;
+    // row_ror:n: the value of lane (g - n) mod 16 of the row, the lower lane when g >= n
+    count(dpp<0x121>(key), g >= 1);
+    count(dpp<0x122>(key), g >= 2);
+    count(dpp<0x123>(key), g >= 3);
+    count(dpp<0x124>(key), g >= 4);
+    count(dpp<0x125>(key), g >= 5);
+    count(dpp<0x126>(key), g >= 6);
+    count(dpp<0x127>(key), g >= 7);
+    count(dpp<0x128>(key), g >= 8);
+    count(dpp<0x129>(key), g >= 9);
+    count(dpp<0x12A>(key), g >= 10);
+    count(dpp<0x12B>(key), g >= 11);
+    count(dpp<0x12C>(key), g >= 12);
+    count(dpp<0x12D>(key), g >= 13);
+    count(dpp<0x12E>(key), g >= 14);
+    count(dpp<0x12F>(key), g >= 15);
+  } else {
+    static_assert(G2 == 2 || G2 == 4 || G2 == 8, "groups of 2, 4, 8 or 16 lanes");
+    // lane xor m is the lower lane when the lane has the highest bit of m set
+    count(dpp<0xB1>(key), lane & 1);  // xor 1: quad_perm [1,0,3,2]
+    if constexpr (G2 >= 4) {
+      count(dpp<0x4E>(key), lane & 2);  // xor 2: quad_perm [2,3,0,1]
+      count(dpp<0x1B>(key), lane & 2);  // xor 3: quad_perm [3,2,1,0]
+    }
+    if constexpr (G2 == 8) {
+      const uint32_t m7 = dpp<0x141>(key);  // xor 7: row_half_mirror
+      count(m7, lane & 4);
+      count(dpp<0x1B>(m7), lane & 4);  // xor 4 = xor 7, then xor 3
+      count(dpp<0x4E>(m7), lane & 4);  // xor 5 = xor 7, then xor 2
+      count(dpp<0xB1>(m7), lane & 4);  // xor 6 = xor 7, then xor 1
+    }
+  }
+  return r;
+}
+
 // Value x of stage n - K on a list entry's path at leaf i, recomputed from the channel
 // LLRs (the entry's frame at root + rofs): f of the two halves of the stage above in an
 // even node, g of them with the kept partial sums of the node's left sibling (level K of
@@ -280,16 +327,11 @@ __device__ __forceinline__ void scl_frames(const CodeArgs& code, const FrameJob&
     const uint32_t cpm0 = (uint32_t)__builtin_amdgcn_ds_bpermute(cl << 2, (int)pm);
     const bool chd = TR::hd(ca);
     const uint32_t cpm = (cval && (cu != 0) != chd) ? TR::pm_add(cpm0, TR::mag(ca)) : cpm0;
-    // rank among the frame's candidates by (metric, candidate number); unused candidates
-    // hold the largest key, above every metric, so that they are never counted
+    // rank among the frame's candidates (its aligned group of 2 L lanes) by (metric,
+    // candidate number); unused candidates hold the largest key, above every metric, so
+    // that they are never counted
     const uint32_t key = cval ? cpm : 0xFFFFFFFFu;
-    int rank = 0;
-#pragma unroll
-    for (int c = 0; c < 2 * LW; ++c) {
-      const uint32_t o = readlane(key, c);
-      const bool mine = F == 1 || (c >> (lgL + 1)) == cf;
-      rank += (mine && (o < key || (o == key && c < lane))) ? 1 : 0;
-    }
+    const int rank = group_rank<2 * L>(key, lane);
     const int n2 = 2 * n < L ? 2 * n : L;
     const bool surv = cval && rank < n2;
     // the first child of a parent (the lower new position of the two candidates) keeps the
