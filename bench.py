@@ -358,7 +358,7 @@ def main():
     if args.workload == "sweep" and (args.D, args.L) != (D, L):
         sweep_config(args.D, args.L)
     if args.gpus != 1:
-        print("bench.py: this build decodes on one GPU; --gpus %d is not supported (frames are "
+        print("bench.py: the library decodes on one GPU; --gpus %d is not supported (frames are "
               "independent, see the design notes for how the batch would shard)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

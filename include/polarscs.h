@@ -33,7 +33,7 @@ enum {
   POLAR_EINVAL = -1,       /* invalid argument */
   POLAR_ENOMEM = -2,       /* host or device allocation failed */
   POLAR_EDEVICE = -3,      /* a HIP runtime call failed */
-  POLAR_EUNSUPPORTED = -4  /* valid request outside what this build supports */
+  POLAR_EUNSUPPORTED = -4  /* valid request outside what the library supports */
 };
 
 /* Per-frame status bits written by the decoders. */
