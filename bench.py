@@ -377,7 +377,7 @@ def main():
     code = binding.PolarCode(N, K, CRC, 2.0)
     ctx = binding.ScsContext(0, args.lanes, args.wpb)
     launch_shape = {"lanes_per_frame": args.lanes, "waves_per_block": args.wpb, "source": "flags"}
-    if not (args.lanes or args.wpb) and args.tune != "off" and args.decoder != "scl":
+    if not (args.lanes or args.wpb) and args.tune != "off":
         from paper_1809_03606_amd import tune
 
         dec = args.decoder

@@ -1,9 +1,11 @@
-"""Launch-shape autotuner for the SCS decoder.
+"""Launch-shape autotuner for the decoders.
 
 For one (code, D, L, LLR type) it times every launch shape the library offers -- lanes per
 frame (64: one frame per wavefront; 32 / 16: two / four frames per wavefront) times
 wavefronts per workgroup (1, 2, 4) -- on a sample batch of noisy frames at a
-representative Eb/N0, and keeps the fastest.  Results go to a JSON cache keyed by device
+representative Eb/N0, and keeps the fastest.  The fast stack decoder offers the
+one-frame-per-wavefront form only; the list decoder (which packs 8 / L frames into a
+wavefront at L <= 4 by itself, and ignores D) the workgroup size only.  Results go to a JSON cache keyed by device
 architecture, N, K, CRC bits, D, L and LLR type (default file: $POLARSCS_TUNE_CACHE or
 ~/.cache/polarscs/tune.json), and ``apply`` configures a decoder context from it.  Entries
 shipped with the package (``tuned.json``, written by this module's command line on an
@@ -37,13 +39,15 @@ def _arch(torch) -> str:
 
 
 def key(arch: str, code, D: int, L: int, dtype: str, decoder: str = "scs") -> str:
+    if decoder == "scl":
+        D = 0  # the list decoder has no stack
     k = "%s:N%d:K%d:crc%d:D%d:L%d:%s" % (arch, code.N, code.K, code.crc_bits, D, L, dtype)
     return k if decoder == "scs" else k + ":" + decoder
 
 
 def candidates(decoder: str = "scs"):
     """Launch shapes: (lanes per frame, wavefronts per workgroup).  The fast decoder has
-    the one-frame-per-wavefront form only."""
+    the one-frame-per-wavefront form only, the list decoder the workgroup size only."""
     return CANDIDATES if decoder == "scs" else [c for c in CANDIDATES if c[0] == 64]
 
 
@@ -76,8 +80,12 @@ def save(entries: dict, path: str | None = None):
 def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames: int = 65536,
          reps: int = 2, seed: int = 7, path: str | None = None, verbose: bool = False,
          decoder: str = "scs") -> dict:
-    """Time every launch shape on `frames` noisy frames; store and return the best."""
+    """Time every launch shape on `frames` noisy frames (for the list decoder at L < 8,
+    8 / L times as many: the same number of wavefronts); store and return the best."""
     import torch
+
+    if decoder == "scl" and L < 8:
+        frames *= 8 // L
 
     dev = torch.device("cuda", 0)
     gen = torch.Generator(device=dev)
@@ -101,7 +109,10 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
         for r in range(reps + 1):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            ctx.decode(code, D, L, llr, out, st, None, stream, fast=fast)
+            if decoder == "scl":
+                ctx.decode_list(code, L, llr, out, st, None, stream)
+            else:
+                ctx.decode(code, D, L, llr, out, st, None, stream, fast=fast)
             b.record(stream)
             stream.synchronize()
             if r:
@@ -146,12 +157,12 @@ def main(argv=None):
     ap.add_argument("--N", type=int, required=True)
     ap.add_argument("--K", type=int, required=True)
     ap.add_argument("--crc", type=int, default=16)
-    ap.add_argument("--D", type=int, required=True)
+    ap.add_argument("--D", type=int, default=32, help="stack depth (not used by the list decoder)")
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
     ap.add_argument("--ebn0", type=float, default=2.0)
     ap.add_argument("--frames", type=int, default=65536)
-    ap.add_argument("--decoder", choices=("scs", "fsscs"), default="scs")
+    ap.add_argument("--decoder", choices=("scs", "fsscs", "scl"), default="scs")
     ap.add_argument("--out", default=None, help="cache file (default: the user cache)")
     a = ap.parse_args(argv)
     code = binding.PolarCode(a.N, a.K, a.crc, 2.0)

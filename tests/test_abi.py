@@ -123,6 +123,10 @@ def test_tune_cache_roundtrip(tmp_path):
     tune.save({k: {"lanes_per_frame": 32, "waves_per_block": 2}}, path)
     assert tune.load(path)[k]["waves_per_block"] == 2
     assert (64, 4) in tune.CANDIDATES and len(tune.CANDIDATES) == 9
+    # the list decoder: no stack depth in its key, workgroup sizes only
+    assert tune.key("gfx950", code, 32, 4, "f32", "scl") == tune.key("gfx950", code, 0, 4, "f32", "scl")
+    assert tune.key("gfx950", code, 32, 4, "f32", "scl").endswith(":D0:L4:f32:scl")
+    assert tune.candidates("scl") == [(64, 4), (64, 2), (64, 1)]
 
 
 def test_library_shares_pytorchs_hip_runtime():

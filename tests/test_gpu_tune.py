@@ -68,3 +68,30 @@ def test_tuner_command_line_in_a_fresh_process(cuda, tmp_path):
     assert (entry["lanes_per_frame"], entry["waves_per_block"]) in [
         tuple(c) for c in __import__("paper_1809_03606_amd.tune", fromlist=["x"]).CANDIDATES]
     assert json.load(open(out))
+
+
+def test_tuner_list_decoder(cuda, tmp_path):
+    """The list decoder's workgroup size through the tuner: a stored choice among its
+    candidates, applied to a context that still decodes to the oracle's bits."""
+    import oracle
+    from paper_1809_03606_amd import binding, tune
+
+    code = binding.PolarCode(256, 128, 16)
+    path = str(tmp_path / "tune.json")
+    print("gpu: tuner, list decoder L=4 on PC(256,128)", flush=True)
+    entry = tune.tune(code, 0, 4, "f32", frames=2048, reps=1, path=path, decoder="scl")
+    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in tune.candidates("scl")
+    assert entry["frames"] == 2048 * 2  # two frames per wavefront at L = 4
+    ctx = binding.ScsContext(0)
+    assert tune.apply(ctx, code, 32, 4, "f32", path=path, decoder="scl") is not None
+    info, pay, llr = make_frames(256, 128, 16, 2.0, 41, seed=6)
+    rp, rs, _ = oracle.scl_decode_batch(oracle.F32, info, 16, 4, llr, threads=4)
+    torch = cuda
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(llr).to(dev)
+    out = torch.empty((41, code.payload_bits), dtype=torch.uint8, device=dev)
+    st = torch.empty((41,), dtype=torch.uint8, device=dev)
+    ctx.decode_list(code, 4, x, out, st)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert np.array_equal(out.cpu().numpy(), rp) and np.array_equal(st.cpu().numpy(), rs)
