@@ -788,17 +788,25 @@ DEPTHS = (8, 16, 32, 64, 128, 256)
 
 def run_depth(args):
     """Stack depth and L: FER and throughput of SCS and FSSCS-RM on the same 10^6 noisy
-    frames of PC(1024,512)+CRC-16 at 2 dB (and 3 dB), for D in {8, 16, 32, 64, 128, 256} and
-    L in {2, 4, 8}, with CA-SCL (L in {1, 2, 4, 8}) on the same frames."""
+    frames of PC(1024,512)+CRC-16 at each Eb/N0 point, for D in {8, 16, 32, 64, 128, 256}
+    and L in {2, 4, 8}, with CA-SCL (L in {1, 2, 4, 8}) on the same frames; every
+    configuration at the autotuner's stored workgroup size where there is one."""
     import torch
 
-    from paper_1809_03606_amd import binding, channel
+    from paper_1809_03606_amd import binding, channel, tune
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     B, kp = args.frames, K - CRC
     code = binding.PolarCode(N, K, CRC, 2.0)
     ctx = binding.ScsContext(0, 64, 0)
+
+    def shape(dec, d, lp):
+        """The autotuner's stored workgroup size for this configuration, else the default."""
+        ctx.configure(64, 0)
+        e = tune.apply(ctx, code, d, lp, "f32", decoder=dec)
+        return e["waves_per_block"] if e else 0
+
     stream = torch.cuda.Stream(device=dev)
     out = torch.empty((B, kp), dtype=torch.uint8, device=dev)
     st = torch.empty((B,), dtype=torch.uint8, device=dev)
@@ -820,6 +828,7 @@ def run_depth(args):
             fn = binding.fsscs_decode_batch if dec == "fsscs" else binding.scs_decode_batch
             for d in DEPTHS:
                 for Lp in (2, 4, 8):
+                    wpb = shape(dec, d, Lp)
                     fn(ctx.handle, code.handle, d, Lp, binding.SCS_LLR_F32, llr, B, out, st,
                        None, stream)  # warm-up
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -832,10 +841,12 @@ def run_depth(args):
                     errs = int((out != pay).any(dim=1).sum().item())
                     rows.append({"decoder": dec, "ebn0_db": eb, "D": d, "L": Lp, "fer": errs / B,
                                  "fer_ci95": wilson(errs, B), "launch_ms": ms,
-                                 "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
+                                 "payload_mbps": B * kp / (ms * 1e-3) / 1e6,
+                                 "waves_per_block": wpb or "default"})
                     log("depth: %s Eb/N0 %.1f D=%d L=%d FER %.5f %.0f Mbit/s" % (
                         dec, eb, d, Lp, errs / B, rows[-1]["payload_mbps"]))
         for Lp in (1, 2, 4, 8):
+            wpb = shape("scl", 0, Lp)
             binding.scl_decode_batch(ctx.handle, code.handle, Lp, binding.SCS_LLR_F32, llr, B, out,
                                      st, None, stream)  # warm-up
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -848,7 +859,8 @@ def run_depth(args):
             errs = int((out != pay).any(dim=1).sum().item())
             rows.append({"decoder": "scl", "ebn0_db": eb, "D": None, "L": Lp, "fer": errs / B,
                          "fer_ci95": wilson(errs, B), "launch_ms": ms,
-                         "payload_mbps": B * kp / (ms * 1e-3) / 1e6})
+                         "payload_mbps": B * kp / (ms * 1e-3) / 1e6,
+                         "waves_per_block": wpb or "default"})
             log("depth: scl Eb/N0 %.1f L=%d FER %.5f %.0f Mbit/s" % (
                 eb, Lp, errs / B, rows[-1]["payload_mbps"]))
         del llr, pay
