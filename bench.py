@@ -65,8 +65,6 @@ def parse():
                     help="frames per point decoded by the CPU oracle for cpu_baseline (0: skip; "
                          "default 40000, 8000 for the list decoder, whose oracle is slower)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
-    ap.add_argument("--lanes", type=int, default=0, choices=(0, 16, 32, 64),
-                    help="lanes per frame (0: the autotuner's choice, see --tune)")
     ap.add_argument("--wpb", type=int, default=0, choices=(0, 1, 2, 4),
                     help="wavefronts per workgroup (0: the autotuner's choice)")
     ap.add_argument("--decoder", choices=("scs", "fsscs", "scl"), default="scs",
@@ -108,8 +106,7 @@ def parse():
 
 
 KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
-                  "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h",
-                  "paper_1809_03606_amd/csrc/scs_rows.hip")
+                  "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
 COUNTERS_RECORD = os.path.join(ROOT, "profiles", "decoder_counters_n1024.json")
 CU_CYCLES_PER_S = 256 * 2.4e9  # MI355X: 256 CUs at 2.4 GHz
@@ -375,9 +372,9 @@ def main():
     kp = K - CRC
 
     code = binding.PolarCode(N, K, CRC, 2.0)
-    ctx = binding.ScsContext(0, args.lanes, args.wpb)
-    launch_shape = {"lanes_per_frame": args.lanes, "waves_per_block": args.wpb, "source": "flags"}
-    if not (args.lanes or args.wpb) and args.tune != "off":
+    ctx = binding.ScsContext(0, args.wpb)
+    launch_shape = {"waves_per_block": args.wpb, "source": "flags"}
+    if not args.wpb and args.tune != "off":
         from paper_1809_03606_amd import tune
 
         dec = args.decoder
@@ -388,8 +385,7 @@ def main():
             entry = tune.tune(code, D, L, args.dtype, decoder=dec)
             tune.apply(ctx, code, D, L, args.dtype, decoder=dec)
             source = "tuned in %.1f s" % (time.time() - t0)
-        launch_shape = {"lanes_per_frame": entry["lanes_per_frame"],
-                        "waves_per_block": entry["waves_per_block"], "source": source,
+        launch_shape = {"waves_per_block": entry["waves_per_block"], "source": source,
                         "candidates_ms": entry["candidates_ms"]}
         log("launch shape: %s" % launch_shape)
     stream = torch.cuda.Stream(device=dev)
@@ -502,12 +498,11 @@ def main():
     # the counter records were taken on the binary32 SCS kernel at 64 lanes per frame, on
     # the headline configuration
     recorded = (not fast and not scl and args.dtype == "f32"
-                and launch_shape["lanes_per_frame"] in (0, 64) and (D, L) == HEADLINE_DL)
+                and (D, L) == HEADLINE_DL)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                 "frac": achieved / peak, "traffic": measured_traffic(B) if recorded else None,
                 "kernel": ("fsscs_uniform_kernel" if fast else "scl_uniform_kernel" if scl else
-                           "scs_uniform_kernel" if launch_shape["lanes_per_frame"] in (0, 64)
-                           else "scs_rows_kernel<%d>" % launch_shape["lanes_per_frame"])
+                           "scs_uniform_kernel")
                           + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
                 "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch,
                 "issue": issue_bound(per_point, B) if recorded else None}
@@ -799,11 +794,11 @@ def run_depth(args):
     torch.cuda.set_device(dev)
     B, kp = args.frames, K - CRC
     code = binding.PolarCode(N, K, CRC, 2.0)
-    ctx = binding.ScsContext(0, 64, 0)
+    ctx = binding.ScsContext(0)
 
     def shape(dec, d, lp):
         """The autotuner's stored workgroup size for this configuration, else the default."""
-        ctx.configure(64, 0)
+        ctx.configure(0)
         e = tune.apply(ctx, code, d, lp, "f32", decoder=dec)
         return e["waves_per_block"] if e else 0
 

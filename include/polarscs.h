@@ -94,12 +94,6 @@ typedef struct scs_ctx scs_ctx; /* per-device decoder context */
 int scs_ctx_create(int device, scs_ctx** out);
 void scs_ctx_destroy(scs_ctx* ctx);
 
-/* Lanes of a 64-lane wavefront given to one frame: 16 or 32 (several frames share a
- * wavefront and its vector instructions) or 64 (one frame per wavefront); 0 lets the
- * library choose (64; 16 and 32 fall back to 64 when their LDS state would not fit or D > 64).
- * Results do not depend on this setting.  Errors: POLAR_EINVAL for any other value. */
-int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame);
-
 /* Wavefronts per workgroup of the decoder launches: 1, 2 or 4, or 0 for the library's
  * choice (4, fewer when their LDS state would exceed 64 KB).  A launch never uses more
  * than fit.  Results do not depend on this setting.  Errors: POLAR_EINVAL otherwise. */

@@ -24,7 +24,7 @@ SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
-           "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
+           "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch",
            "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
            "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch")
 
@@ -87,7 +87,6 @@ def lib():
             L.scs_mixed_prepare.argtypes = [vp, vp, i32, vp, i64, vp]
             L.scs_mixed_launch.argtypes = [vp, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
-            L.scs_ctx_set_lanes.argtypes = [vp, i32]
             L.scs_ctx_set_waves_per_block.argtypes = [vp, i32]
             L.polar_code_schedule.argtypes = [vp, vp]
             L.fsscs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
@@ -96,7 +95,7 @@ def lib():
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
-                      "scs_mixed_prepare", "scs_mixed_launch", "scs_ctx_set_lanes",
+                      "scs_mixed_prepare", "scs_mixed_launch",
                       "scs_ctx_set_waves_per_block", "scs_ctx_last_error",
                       "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch"):
                 getattr(L, n).restype = ctypes.c_int
@@ -250,10 +249,6 @@ def scs_mixed_launch(ctx: int, llr_dtype: int, llr_dev, payload_dev, status_dev,
            "scs_mixed_launch")
 
 
-def scs_ctx_set_lanes(ctx: int, lanes_per_frame: int):
-    _check(lib().scs_ctx_set_lanes(ctx, int(lanes_per_frame)), "scs_ctx_set_lanes")
-
-
 def scs_ctx_set_waves_per_block(ctx: int, waves_per_block: int):
     _check(lib().scs_ctx_set_waves_per_block(ctx, int(waves_per_block)),
            "scs_ctx_set_waves_per_block")
@@ -310,16 +305,13 @@ class PolarCode:
 
 
 class ScsContext:
-    def __init__(self, device: int = 0, lanes_per_frame: int = 0, waves_per_block: int = 0):
+    def __init__(self, device: int = 0, waves_per_block: int = 0):
         self.handle = scs_ctx_create(device)
         self.device = device
-        if lanes_per_frame:
-            scs_ctx_set_lanes(self.handle, lanes_per_frame)
         if waves_per_block:
             scs_ctx_set_waves_per_block(self.handle, waves_per_block)
 
-    def configure(self, lanes_per_frame: int = 0, waves_per_block: int = 0):
-        scs_ctx_set_lanes(self.handle, lanes_per_frame)
+    def configure(self, waves_per_block: int = 0):
         scs_ctx_set_waves_per_block(self.handle, waves_per_block)
 
     def _frames(self, code: PolarCode, llr_dev, payload_dev, status_dev, stats_dev):

@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["polar_code.cpp", "scs_decode.hip", "scs_rows.hip", "fsscs_decode.hip", "scl_decode.hip"]
+SOURCES = ["polar_code.cpp", "scs_decode.hip", "fsscs_decode.hip", "scl_decode.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall",
           "-fno-fast-math", "-ffp-contract=off"]

@@ -520,7 +520,6 @@ int device_table(const polar_code* code, CodeTable which, const T** out) {
 
 struct scs_ctx {
   int device = 0;
-  int lanes = 0;  // lanes per frame: 0 = automatic, else 16, 32 or 64
   int wpb = 0;    // wavefronts per workgroup: 0 = automatic, else 1, 2 or 4
   int last_error = POLAR_OK;
   int cus = 0;    // compute units of the device
@@ -543,20 +542,6 @@ struct scs_ctx {
 namespace {
 
 constexpr size_t kMaxLdsPerBlock = 64 * 1024;
-
-// Lanes per frame for a launch.  Measured on MI355X (PC(1024,512), D = 32): one frame
-// per wavefront is fastest, so it is the automatic choice; 16 / 32 are taken on request.
-int choose_lanes(const scs_ctx* ctx, int N, int D) {
-  const int want = ctx->lanes;
-  auto fits = [&](int G) {
-    if (G == 64) return true;
-    if (G == 16 && D > 64) return false;
-    if (G == 32 && D > 64) return false;
-    return polarscs::rows_lds_bytes(N, D, G, 1) <= kMaxLdsPerBlock;
-  };
-  if (want == 16 || want == 32 || want == 64) return fits(want) ? want : 64;
-  return 64;
-}
 
 }  // namespace
 
@@ -601,16 +586,6 @@ void scs_ctx_destroy(scs_ctx* ctx) {
   delete ctx;
 }
 
-int scs_ctx_set_lanes(scs_ctx* ctx, int32_t lanes_per_frame) {
-  if (!ctx) return POLAR_EINVAL;
-  if (lanes_per_frame != 0 && lanes_per_frame != 16 && lanes_per_frame != 32 &&
-      lanes_per_frame != 64)
-    return POLAR_EINVAL;
-  std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->lanes = lanes_per_frame;
-  return POLAR_OK;
-}
-
 int scs_ctx_set_waves_per_block(scs_ctx* ctx, int32_t waves_per_block) {
   if (!ctx) return POLAR_EINVAL;
   if (waves_per_block != 0 && waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
@@ -644,33 +619,6 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   CodeArgs args = make_args(code);
   if (const int e = device_table(code, kTabCrcSyn, &args.crc_tab)) return e;
   hipStream_t s = (hipStream_t)hip_stream;
-  const int G = choose_lanes(ctx, code->N, D);
-  if (G != 64) {
-    polarscs::RowsLaunch a;
-    a.code = args;
-    a.G = G;
-    a.D = D;
-    a.L = L;
-    a.dtype = llr_dtype;
-    a.waves_per_block = 1;
-    const int cap = ctx->wpb ? ctx->wpb : 4;
-    while (a.waves_per_block < cap &&
-           polarscs::rows_lds_bytes(code->N, D, G, a.waves_per_block * 2) <= kMaxLdsPerBlock)
-      a.waves_per_block *= 2;
-    a.llr = llr_dev;
-    a.n_frames = n_frames;
-    a.payload = payload_dev;
-    a.status = status_dev;
-    a.stats = stats_dev;
-    a.stream = s;
-    const hipError_t e = polarscs::launch_rows(a);
-    if (e != hipSuccess) {
-      std::lock_guard<std::mutex> g(ctx->mu);
-      ctx->last_error = POLAR_EDEVICE;
-      return POLAR_EDEVICE;
-    }
-    return POLAR_OK;
-  }
   int wpb = waves_per_block(code->N, D);
   if (ctx->wpb && ctx->wpb < wpb) wpb = ctx->wpb;
   const int wave_words = lds_words_per_wave(code->N, D);

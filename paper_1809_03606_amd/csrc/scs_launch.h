@@ -7,19 +7,6 @@
 
 namespace polarscs {
 
-struct RowsLaunch {
-  CodeArgs code;
-  int G;                // lanes per frame: 16 or 32
-  int D, L, dtype;
-  int waves_per_block;
-  const void* llr;
-  int64_t n_frames;
-  uint8_t* payload;
-  uint8_t* status;
-  scs_stats* stats;
-  hipStream_t stream;
-};
-
 struct FsscsLaunch {
   CodeArgs code;  // nodes and crc_tab set
   int D, L, dtype;
@@ -50,10 +37,5 @@ struct SclLaunch {
 // LDS bytes of one frame of the list decoder, and the launcher.
 size_t scl_lds_bytes(int N, int L);
 hipError_t launch_scl(const SclLaunch& a);
-
-// LDS bytes of one workgroup of the several-frames-per-wavefront kernel.
-size_t rows_lds_bytes(int N, int D, int G, int waves_per_block);
-// Enqueue the several-frames-per-wavefront decoder.
-hipError_t launch_rows(const RowsLaunch& a);
 
 }  // namespace polarscs

@@ -1,11 +1,9 @@
 """Launch-shape autotuner for the decoders.
 
-For one (code, D, L, LLR type) it times every launch shape the library offers -- lanes per
-frame (64: one frame per wavefront; 32 / 16: two / four frames per wavefront) times
+For one (code, D, L, LLR type) it times every launch shape the library offers --
 wavefronts per workgroup (1, 2, 4) -- on a sample batch of noisy frames at a
-representative Eb/N0, and keeps the fastest.  The fast stack decoder offers the
-one-frame-per-wavefront form only; the list decoder (which packs 8 / L frames into a
-wavefront at L <= 4 by itself, and ignores D) the workgroup size only.  Results go to a JSON cache keyed by device
+representative Eb/N0, and keeps the fastest.  The list decoder packs 8 / L frames into a
+wavefront at L <= 4 by itself and ignores D.  Results go to a JSON cache keyed by device
 architecture, N, K, CRC bits, D, L and LLR type (default file: $POLARSCS_TUNE_CACHE or
 ~/.cache/polarscs/tune.json), and ``apply`` configures a decoder context from it.  Entries
 shipped with the package (``tuned.json``, written by this module's command line on an
@@ -22,7 +20,7 @@ import time
 
 from . import binding, channel
 
-CANDIDATES = [(lanes, wpb) for lanes in (64, 32, 16) for wpb in (4, 2, 1)]
+CANDIDATES = [4, 2, 1]  # wavefronts per workgroup
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
@@ -46,9 +44,8 @@ def key(arch: str, code, D: int, L: int, dtype: str, decoder: str = "scs") -> st
 
 
 def candidates(decoder: str = "scs"):
-    """Launch shapes: (lanes per frame, wavefronts per workgroup).  The fast decoder has
-    the one-frame-per-wavefront form only, the list decoder the workgroup size only."""
-    return CANDIDATES if decoder == "scs" else [c for c in CANDIDATES if c[0] == 64]
+    """Launch shapes (wavefronts per workgroup); the same for every decoder."""
+    return list(CANDIDATES)
 
 
 def _read(path: str) -> dict:
@@ -103,8 +100,8 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
     times = {}
     ref = None
     fast = decoder == "fsscs"
-    for lanes, wpb in candidates(decoder):
-        ctx.configure(lanes, wpb)
+    for wpb in candidates(decoder):
+        ctx.configure(wpb)
         ms = []
         for r in range(reps + 1):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -120,14 +117,12 @@ def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames:
         if ref is None:
             ref = (out.clone(), st.clone())
         elif not (torch.equal(ref[0], out) and torch.equal(ref[1], st)):
-            raise RuntimeError("launch shape %s changed the decoded bits" % ((lanes, wpb),))
-        times["%d/%d" % (lanes, wpb)] = min(ms)
+            raise RuntimeError("launch shape wpb=%d changed the decoded bits" % wpb)
+        times[str(wpb)] = min(ms)
         if verbose:
-            print("tune %s lanes=%d wpb=%d: %.2f ms" % (key("", code, D, L, dtype, decoder), lanes,
-                                                         wpb, min(ms)))
+            print("tune %s wpb=%d: %.2f ms" % (key("", code, D, L, dtype, decoder), wpb, min(ms)))
     best = min(times, key=times.get)
-    lanes, wpb = (int(x) for x in best.split("/"))
-    entry = {"lanes_per_frame": lanes, "waves_per_block": wpb, "ms": times[best],
+    entry = {"waves_per_block": int(best), "ms": times[best],
              "candidates_ms": times, "frames": frames, "ebn0_db": ebn0_db,
              "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
     entries = _read(path or cache_path())
@@ -144,7 +139,7 @@ def apply(ctx, code, D: int, L: int, dtype: str = "f32", path: str | None = None
 
     entry = load(path).get(key(_arch(torch), code, D, L, dtype, decoder))
     if entry:
-        ctx.configure(entry["lanes_per_frame"], entry["waves_per_block"])
+        ctx.configure(entry["waves_per_block"])
     return entry
 
 

@@ -29,7 +29,7 @@ def oracle_decode(info, crc, D, L, llr):
     return oracle.scs_decode_batch(mode, info, crc, D, L, llr, threads=THREADS)
 
 
-def gpu_decode(torch, code, D, L, llr, with_stats=True, ctx=None, lanes=0, wpb=0, fast=False):
+def gpu_decode(torch, code, D, L, llr, with_stats=True, ctx=None, wpb=0, fast=False):
     from paper_1809_03606_amd import binding
 
     B = llr.shape[0]
@@ -40,7 +40,7 @@ def gpu_decode(torch, code, D, L, llr, with_stats=True, ctx=None, lanes=0, wpb=0
     stats = torch.zeros((max(B, 1), 8), dtype=torch.int32, device=dev) if with_stats else None
     own = ctx is None
     if own:
-        ctx = binding.ScsContext(0, lanes, wpb)
+        ctx = binding.ScsContext(0, wpb)
     ctx.decode(code, D, L, x, pay, st, stats, fast=fast)
     torch.cuda.synchronize()
     out = (pay[:B].cpu().numpy(), st[:B].cpu().numpy(),

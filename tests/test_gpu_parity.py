@@ -19,20 +19,17 @@ def _say(msg):
     sys.stdout.flush()
 
 
-LANES = [16, 32, 64]
-
-
-def _run(cuda, N, K, crc, D, L, ebn0, B, seed, dtype="f32", label=None, lanes=0):
+def _run(cuda, N, K, crc, D, L, ebn0, B, seed, dtype="f32", label=None):
     from paper_1809_03606_amd.binding import PolarCode
 
     label = (label or "N=%d K=%d crc=%d D=%d L=%d Eb/N0=%.1f B=%d seed=%d %s" % (
-        N, K, crc, D, L, ebn0, B, seed, dtype)) + " lanes=%d" % lanes
+        N, K, crc, D, L, ebn0, B, seed, dtype))
     info, pay, llr = make_frames(N, K, crc, ebn0, B, seed, dtype=dtype)
     code = PolarCode(N, K, crc, 2.0)
     assert (code.info_mask == info).all()
     ref = oracle_decode(info, crc, D, L, llr)
     _say("gpu: " + label)
-    got = gpu_decode(cuda, code, D, L, llr, lanes=lanes)
+    got = gpu_decode(cuda, code, D, L, llr)
     assert_parity(got, ref, label)
     return got, ref, pay
 
@@ -55,7 +52,7 @@ SMALL = [
 
 # Stacks deeper than one 64-slot bank (D up to 256): low Eb/N0 and large L so that the
 # stack fills past 64 slots, evicts and drops; D just above a bank boundary; a tiny code
-# under a huge stack.  A request for 16 or 32 lanes per frame runs 64 lanes for these.
+# under a huge stack.
 DEEP = [
     (16, 8, 0, 256, 255, 0.0), (64, 32, 0, 65, 8, 1.0), (128, 64, 16, 100, 8, 1.0),
     (256, 128, 16, 128, 16, 1.0), (512, 256, 16, 200, 16, 1.0), (1024, 512, 16, 256, 8, 1.0),
@@ -72,44 +69,36 @@ def test_gpu_deep_stack_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
 @pytest.mark.parametrize("N,K,crc,D,L,eb", DEEP[1::2])
 def test_gpu_deep_stack_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
     B = 37 if N >= 1024 else 101
-    _run(cuda, N, K, crc, D, L, eb, B, seed=61 + N + D, dtype="i8", lanes=16)
+    _run(cuda, N, K, crc, D, L, eb, B, seed=61 + N + D, dtype="i8")
 
 
-@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("N,K,crc,D,L,eb", SMALL)
-def test_gpu_matches_oracle_f32(cuda, N, K, crc, D, L, eb, lanes):
+def test_gpu_matches_oracle_f32(cuda, N, K, crc, D, L, eb):
     B = 37 if N >= 1024 else 101
-    _run(cuda, N, K, crc, D, L, eb, B, seed=11 + N, lanes=lanes)
+    _run(cuda, N, K, crc, D, L, eb, B, seed=11 + N)
 
 
-@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("N,K,crc,D,L,eb", SMALL[::2])
-def test_gpu_matches_oracle_i8(cuda, N, K, crc, D, L, eb, lanes):
+def test_gpu_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
     B = 37 if N >= 1024 else 101
-    _run(cuda, N, K, crc, D, L, eb, B, seed=23 + N, dtype="i8", lanes=lanes)
+    _run(cuda, N, K, crc, D, L, eb, B, seed=23 + N, dtype="i8")
 
 
-@pytest.mark.parametrize("lanes", LANES)
-def test_gpu_plain_scs_n64(cuda, lanes):
+def test_gpu_plain_scs_n64(cuda):
     """Plain SCS, N=64, K=32, no CRC, D=8, L=8, Eb/N0 2 dB, 10,000 frames."""
-    got, ref, pay = _run(cuda, 64, 32, 0, 8, 8, 2.0, 10000, seed=1, label="plain SCS N=64 10k",
-                         lanes=lanes)
+    got, ref, pay = _run(cuda, 64, 32, 0, 8, 8, 2.0, 10000, seed=1, label="plain SCS N=64 10k")
     assert (got[1] == 1).all()
 
 
-@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("eb", [1.0, 1.5, 2.0, 2.5, 3.0])
-def test_gpu_n1024_crc16_points(cuda, eb, lanes):
+def test_gpu_n1024_crc16_points(cuda, eb):
     """N=1024, K=512 with CRC-16, D=32, L=8 at each Eb/N0 point of the sweep."""
-    _run(cuda, 1024, 512, 16, 32, 8, eb, 300, seed=2, label="N=1024 sweep %.1f dB" % eb,
-         lanes=lanes)
+    _run(cuda, 1024, 512, 16, 32, 8, eb, 300, seed=2, label="N=1024 sweep %.1f dB" % eb)
 
 
-@pytest.mark.parametrize("lanes", LANES)
-def test_gpu_fixed_point_n1024(cuda, lanes):
+def test_gpu_fixed_point_n1024(cuda):
     """int8 LLRs / int16 path metrics at 2 dB, N=1024, K=512 + CRC-16, D=32."""
-    _run(cuda, 1024, 512, 16, 32, 8, 2.0, 300, seed=2, dtype="i8", label="fixed point N=1024",
-         lanes=lanes)
+    _run(cuda, 1024, 512, 16, 32, 8, 2.0, 300, seed=2, dtype="i8", label="fixed point N=1024")
 
 
 def test_gpu_fixed_point_saturation(cuda):

@@ -9,17 +9,16 @@ from cases import assert_parity, gpu_decode, make_frames, oracle_decode
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("lanes", [16, 32, 64])
 @pytest.mark.parametrize("wpb", [1, 2, 4])
-def test_every_launch_shape_matches_oracle(cuda, lanes, wpb):
+def test_every_launch_shape_matches_oracle(cuda, wpb):
     from paper_1809_03606_amd.binding import PolarCode
 
     N, K, crc, D, L = 512, 256, 16, 32, 8
     info, pay, llr = make_frames(N, K, crc, 1.5, 53, seed=97)
     ref = oracle_decode(info, crc, D, L, llr)
-    print("gpu: launch shape lanes=%d wpb=%d" % (lanes, wpb), flush=True)
-    got = gpu_decode(cuda, PolarCode(N, K, crc, 2.0), D, L, llr, lanes=lanes, wpb=wpb)
-    assert_parity(got, ref, "lanes=%d wpb=%d" % (lanes, wpb))
+    print("gpu: launch shape wpb=%d" % wpb, flush=True)
+    got = gpu_decode(cuda, PolarCode(N, K, crc, 2.0), D, L, llr, wpb=wpb)
+    assert_parity(got, ref, "wpb=%d" % wpb)
 
 
 def test_tuner_stores_and_applies(cuda, tmp_path):
@@ -29,11 +28,11 @@ def test_tuner_stores_and_applies(cuda, tmp_path):
     path = str(tmp_path / "tune.json")
     print("gpu: tuner on PC(256,128)", flush=True)
     entry = tune.tune(code, 16, 8, "f32", frames=4096, reps=1, path=path)
-    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in tune.CANDIDATES
+    assert entry["waves_per_block"] in tune.CANDIDATES
     assert len(entry["candidates_ms"]) == len(tune.CANDIDATES)
     ctx = binding.ScsContext(0)
     got = tune.apply(ctx, code, 16, 8, "f32", path=path)
-    assert got["lanes_per_frame"] == entry["lanes_per_frame"]
+    assert got["waves_per_block"] == entry["waves_per_block"]
     assert tune.apply(ctx, binding.PolarCode(128, 64, 0), 16, 8, "f32", path=path) is None
     # the configured context still decodes to the oracle's bits
     info, pay, llr = make_frames(256, 128, 16, 2.0, 40, seed=5)
@@ -65,8 +64,8 @@ def test_tuner_command_line_in_a_fresh_process(cuda, tmp_path):
                        cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     entry = json.loads(r.stdout.strip().splitlines()[-1])
-    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in [
-        tuple(c) for c in __import__("paper_1809_03606_amd.tune", fromlist=["x"]).CANDIDATES]
+    assert entry["waves_per_block"] in __import__("paper_1809_03606_amd.tune",
+                                                 fromlist=["x"]).CANDIDATES
     assert json.load(open(out))
 
 
@@ -80,7 +79,7 @@ def test_tuner_list_decoder(cuda, tmp_path):
     path = str(tmp_path / "tune.json")
     print("gpu: tuner, list decoder L=4 on PC(256,128)", flush=True)
     entry = tune.tune(code, 0, 4, "f32", frames=2048, reps=1, path=path, decoder="scl")
-    assert (entry["lanes_per_frame"], entry["waves_per_block"]) in tune.candidates("scl")
+    assert entry["waves_per_block"] in tune.candidates("scl")
     assert entry["frames"] == 2048 * 2  # two frames per wavefront at L = 4
     ctx = binding.ScsContext(0)
     assert tune.apply(ctx, code, 32, 4, "f32", path=path, decoder="scl") is not None
