@@ -33,7 +33,8 @@ enum {
   POLAR_EINVAL = -1,       /* invalid argument */
   POLAR_ENOMEM = -2,       /* host or device allocation failed */
   POLAR_EDEVICE = -3,      /* a HIP runtime call failed */
-  POLAR_EUNSUPPORTED = -4  /* valid request outside what the library supports */
+  POLAR_EUNSUPPORTED = -4, /* valid request outside what the library supports */
+  POLAR_ETOOLARGE = -5     /* request beyond a fixed capacity (scs_decode_mixed_noalloc) */
 };
 
 /* Per-frame status bits written by the decoders. */
@@ -171,6 +172,31 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
                       const scs_frame* frames_host, int64_t n_frames, void* hip_stream);
 int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8_t* payload_dev,
                      uint8_t* status_dev, scs_stats* stats_dev, void* hip_stream);
+
+/* Fixed capacity of scs_decode_mixed_noalloc. */
+#define SCS_NOALLOC_SCRATCH_BYTES (16u << 20) /* per device, held while the library is loaded */
+#define SCS_NOALLOC_MAX_CODES 64
+
+/* For callers that cannot allocate device memory (code under HIP graph capture of its own
+ * stream work, tight serving loops, harnesses that forbid hipMalloc): scs_decode_mixed
+ * without any allocation.  The batch plan -- work counter, the codes' tables and CRC
+ * syndrome tables (64 N bytes per CRC code that a frame uses), and the n_frames
+ * descriptors (24 bytes each) -- goes into one fixed array of SCS_NOALLOC_SCRATCH_BYTES that
+ * the library keeps on every device it runs on, instead of buffers the context grows.  The
+ * call makes no hipMalloc / hipFree and no host-side allocation; it copies the plan from host
+ * memory with hipMemcpyAsync on hip_stream (pageable sources are read before the call
+ * returns, after the stream's earlier work), zeroes the counter with a kernel and launches
+ * the persistent decoder.  Frames are taken in descriptor order (scs_decode_mixed takes the
+ * largest first); every frame's outputs equal what scs_decode_mixed gives.
+ * Arguments, outputs and errors as scs_decode_mixed, plus: POLAR_ETOOLARGE when n_codes
+ * exceeds SCS_NOALLOC_MAX_CODES or the plan exceeds SCS_NOALLOC_SCRATCH_BYTES (nothing is
+ * enqueued then).  All calls on one device share its array and the last call's contents stay
+ * there: calls that overlap on one device (other streams, other contexts, other threads)
+ * race and must be ordered by the caller; calls on one stream are ordered by the stream. */
+int scs_decode_mixed_noalloc(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                             const scs_frame* frames_host, int64_t n_frames, int32_t llr_dtype,
+                             const void* llr_dev, uint8_t* payload_dev, uint8_t* status_dev,
+                             scs_stats* stats_dev, void* hip_stream);
 
 /* The fast simplified schedule of a code (Sections 2.2.2 and 3): nodes_out[N] receives,
  * for the first leaf i of every node, (class << 4) | lambda (the node covers leaves

@@ -19,13 +19,15 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolarscs.so")
 
 POLAR_OK, POLAR_EINVAL, POLAR_ENOMEM, POLAR_EDEVICE, POLAR_EUNSUPPORTED = 0, -1, -2, -3, -4
+POLAR_ETOOLARGE = -5
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_CODES = 16 << 20, 64
 SCS_STATUS_OK, SCS_STATUS_FALLBACK, SCS_STATUS_EXHAUSTED = 1, 2, 4
 SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
 EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch",
-           "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
+           "scs_decode_mixed_noalloc", "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
            "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
@@ -84,6 +86,7 @@ def lib():
             L.scs_ctx_destroy.restype = None
             L.scs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
             L.scs_decode_mixed.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
+            L.scs_decode_mixed_noalloc.argtypes = [vp, vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
             L.scs_mixed_prepare.argtypes = [vp, vp, i32, vp, i64, vp]
             L.scs_mixed_launch.argtypes = [vp, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
@@ -95,6 +98,7 @@ def lib():
             L.polar_strerror.restype = ctypes.c_char_p
             for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
+                      "scs_decode_mixed_noalloc",
                       "scs_mixed_prepare", "scs_mixed_launch",
                       "scs_ctx_set_waves_per_block", "scs_ctx_last_error",
                       "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch"):
@@ -232,6 +236,19 @@ def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_de
                                   fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
                                   _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
                                   _addr(stats_dev), _stream(stream)), "scs_decode_mixed")
+
+
+def scs_decode_mixed_noalloc(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_dev,
+                             payload_dev, status_dev, stats_dev=None, stream=None):
+    """scs_decode_mixed with the batch plan in the library's fixed per-device scratch array
+    (no device allocation); raises PolarError(POLAR_ETOOLARGE) beyond its capacity."""
+    arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
+    fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    _check(lib().scs_decode_mixed_noalloc(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
+                                          fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
+                                          _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
+                                          _addr(stats_dev), _stream(stream)),
+           "scs_decode_mixed_noalloc")
 
 
 def scs_mixed_prepare(ctx: int, codes, frames: np.ndarray, stream=None):

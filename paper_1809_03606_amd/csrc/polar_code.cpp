@@ -116,6 +116,7 @@ const char* polar_strerror(int code) {
     case POLAR_ENOMEM: return "out of memory";
     case POLAR_EDEVICE: return "HIP runtime error";
     case POLAR_EUNSUPPORTED: return "unsupported";
+    case POLAR_ETOOLARGE: return "request exceeds the fixed scratch capacity";
   }
   return "unknown status";
 }

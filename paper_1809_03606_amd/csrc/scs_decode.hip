@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void scs_mixed_kernel(const CodeArgs* __restri
     if (lane == 0) k = atomicAdd(counter, 1u);
     k = readlane(k, 0);
     if (k >= n_frames) break;  // every wave leaves once the queue is empty
-    const int f = order[k];
+    const int f = order ? order[k] : (int)k;  // no order: descriptor order
     const scs_frame d = frames[f];
     const CodeArgs& code = codes[d.code];
     FrameJob job;
@@ -360,6 +360,15 @@ __global__ __launch_bounds__(256) void scs_mixed_kernel(const CodeArgs* __restri
     lds_order();
   }
 }
+
+// ------------------------------------------------------------------------------------
+// Fixed scratch of the no-allocation mixed decoder (scs_decode_mixed_noalloc): the work
+// counter, the code tables, their CRC syndrome tables and the frame descriptors of one
+// batch.  Each device holds its own copy while the library is loaded.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the device (noalloc_scratch).
+// ------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)SCS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 // ------------------------------------------------------------------------------------
 // Device encoder: one wave per frame, lane w owns bits 32w..32w+31 of u.
@@ -537,11 +546,34 @@ struct scs_ctx {
   hipEvent_t staged = nullptr;
   uint32_t plan_frames = 0;
   int plan_wave_words = 0;
+  void* scratch = nullptr;  // device address of this device's fixed scratch array
 };
 
 namespace {
 
 constexpr size_t kMaxLdsPerBlock = 64 * 1024;
+
+// Device address of `scratch` per device, resolved once with that device current (the
+// array's name in host code is only a stand-in for the symbol).  Null until resolved.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Resolves the scratch address of `device`, which is current.  Called at context creation.
+int resolve_scratch(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return POLAR_EUNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return POLAR_EDEVICE;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return POLAR_OK;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -561,8 +593,10 @@ int scs_ctx_create(int device, scs_ctx** out) {
   if (hipSetDevice(device) != hipSuccess ||
       hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipMalloc(&c->d_counter, sizeof(uint32_t)) != hipSuccess ||
-      hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+      resolve_scratch(device, &c->scratch) != POLAR_OK) {
     (void)hipFree(c->d_counter);
+    if (c->staged) (void)hipEventDestroy(c->staged);
     delete c;
     (void)hipSetDevice(dev0);
     return POLAR_EDEVICE;
@@ -866,6 +900,105 @@ int scs_decode_mixed(scs_ctx* ctx, const polar_code* const* codes, int32_t n_cod
   const int rc = scs_mixed_prepare(ctx, codes, n_codes, frames_host, n_frames, hip_stream);
   if (rc != POLAR_OK) return rc;
   return scs_mixed_launch(ctx, llr_dtype, llr_dev, payload_dev, status_dev, stats_dev, hip_stream);
+}
+
+int scs_decode_mixed_noalloc(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
+                             const scs_frame* frames_host, int64_t n_frames, int32_t llr_dtype,
+                             const void* llr_dev, uint8_t* payload_dev, uint8_t* status_dev,
+                             scs_stats* stats_dev, void* hip_stream) {
+  if (!ctx || n_frames < 0 || n_codes < 0) return POLAR_EINVAL;
+  if (llr_dtype != SCS_LLR_F32 && llr_dtype != SCS_LLR_I8) return POLAR_EINVAL;
+  if (n_frames == 0) return POLAR_OK;
+  if (!codes || n_codes < 1 || !frames_host || !llr_dev || !status_dev || !payload_dev)
+    return POLAR_EINVAL;
+  if (n_codes > SCS_NOALLOC_MAX_CODES) return POLAR_ETOOLARGE;
+  for (int32_t c = 0; c < n_codes; ++c)
+    if (!codes[c] || codes[c]->logn < 1 || codes[c]->logn > 11) return POLAR_EINVAL;
+  bool used[SCS_NOALLOC_MAX_CODES] = {};
+  int wave_words = 0;
+  for (int64_t f = 0; f < n_frames; ++f) {
+    const scs_frame& d = frames_host[f];
+    if (d.code < 0 || d.code >= n_codes || d.D < 1 || d.D > 64 || d.L < 1 || d.L > 255 ||
+        d._pad != 0 || d.llr_off < 0 || d.out_off < 0)
+      return POLAR_EINVAL;
+    used[d.code] = true;
+    wave_words = std::max(wave_words, lds_words_per_wave(codes[d.code]->N, d.D));
+  }
+  if ((size_t)wave_words * 4 > kMaxLdsPerBlock) return POLAR_EUNSUPPORTED;
+  // scratch layout: work counter | code tables | CRC syndrome tables | frame descriptors
+  const size_t off_codes = 256;
+  size_t off = align256(off_codes + (size_t)n_codes * sizeof(CodeArgs));
+  size_t crc_off[SCS_NOALLOC_MAX_CODES] = {};
+  for (int32_t c = 0; c < n_codes; ++c) {
+    if (!used[c] || codes[c]->crc == 0) continue;
+    crc_off[c] = off;
+    off = align256(off + codes[c]->crc_syn.size() * sizeof(uint16_t));
+  }
+  const size_t off_frames = off;
+  const size_t need = off_frames + (size_t)n_frames * sizeof(scs_frame);
+  if ((uint64_t)n_frames > 0x7FFFFFFFull || need > kScratchBytes) return POLAR_ETOOLARGE;
+  if (!ctx->scratch) return POLAR_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint8_t* base = (uint8_t*)ctx->scratch;
+  // code tables, built on the host stack; their CRC tables point into the scratch array
+  CodeArgs args[SCS_NOALLOC_MAX_CODES];
+  for (int32_t c = 0; c < n_codes; ++c) {
+    args[c] = make_args(codes[c]);
+    args[c].crc_tab = crc_off[c] ? (const uint16_t*)(base + crc_off[c]) : nullptr;
+  }
+  // Host-to-device copies of pageable memory return once the source has been read, after
+  // the stream's earlier work (which may still read the scratch array) has finished.
+  clear_stale_error();
+  if (hipMemcpyAsync(base + off_codes, args, (size_t)n_codes * sizeof(CodeArgs),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return POLAR_EDEVICE;
+  for (int32_t c = 0; c < n_codes; ++c)
+    if (crc_off[c] &&
+        hipMemcpyAsync(base + crc_off[c], codes[c]->crc_syn.data(),
+                       codes[c]->crc_syn.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+      return POLAR_EDEVICE;
+  if (hipMemcpyAsync(base + off_frames, frames_host, (size_t)n_frames * sizeof(scs_frame),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return POLAR_EDEVICE;
+  int wpb = ctx->wpb ? ctx->wpb : 4;
+  while (wpb > 1 && (size_t)wpb * wave_words * 4 > kMaxLdsPerBlock) wpb >>= 1;
+  const size_t lds = (size_t)wpb * wave_words * 4;
+  const bool st = stats_dev != nullptr;
+  const void* kfun;
+  if (llr_dtype == SCS_LLR_F32)
+    kfun = st ? (const void*)scs_mixed_kernel<TrF32, true> : (const void*)scs_mixed_kernel<TrF32, false>;
+  else
+    kfun = st ? (const void*)scs_mixed_kernel<TrI8, true> : (const void*)scs_mixed_kernel<TrI8, false>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun, 64 * wpb, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int64_t want = (n_frames + wpb - 1) / wpb;
+  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, want);
+  uint32_t* counter = (uint32_t*)base;
+  const CodeArgs* d_codes = (const CodeArgs*)(base + off_codes);
+  const scs_frame* d_frames = (const scs_frame*)(base + off_frames);
+  // the counter keeps the previous call's value: a kernel zeroes it on the stream
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  if (llr_dtype == SCS_LLR_F32) {
+    auto k = st ? scs_mixed_kernel<TrF32, true> : scs_mixed_kernel<TrF32, false>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, d_codes, d_frames,
+                       (const int32_t*)nullptr, (uint32_t)n_frames, (const float*)llr_dev,
+                       payload_dev, status_dev, stats_dev, counter, wave_words);
+  } else {
+    auto k = st ? scs_mixed_kernel<TrI8, true> : scs_mixed_kernel<TrI8, false>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, d_codes, d_frames,
+                       (const int32_t*)nullptr, (uint32_t)n_frames, (const int8_t*)llr_dev,
+                       payload_dev, status_dev, stats_dev, counter, wave_words);
+  }
+  if (hipGetLastError() != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->last_error = POLAR_EDEVICE;
+    return POLAR_EDEVICE;
+  }
+  return POLAR_OK;
 }
 
 int polar_encode_device(const polar_code* code, const uint8_t* payload_dev,
