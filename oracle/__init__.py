@@ -51,12 +51,15 @@ _lock = threading.Lock()
 
 
 def lib():
+    """The compiled oracle.  POLAR_ORACLE_LIB names another build of the same source (the
+    mutation tests load deliberately broken copies this way, in child processes)."""
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB):
+            path = os.environ.get("POLAR_ORACLE_LIB") or _LIB
+            if path == _LIB and not os.path.exists(_LIB):
                 build(force=False)
-            L = ctypes.CDLL(_LIB)
+            L = ctypes.CDLL(path)
             vp, u8p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8)
             L.orc_construct.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, vp]
             L.orc_bhattacharyya_log.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp]
@@ -81,6 +84,11 @@ def lib():
             L.orc_fsscs_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                                  ctypes.c_int64, vp, vp, vp]
+            L.orc_scs_trace.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+            L.orc_fsscs_trace.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                          vp, vp, vp, vp, vp, ctypes.c_int]
             L.orc_scl_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                          vp, vp, vp, vp, vp]
             L.orc_scl_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
@@ -89,7 +97,8 @@ def lib():
                          "orc_encode_batch", "orc_sc_decode", "orc_scs_decode",
                          "orc_scs_decode_batch", "orc_ml_decode", "orc_fssc_schedule",
                          "orc_node_candidates", "orc_fsscs_decode", "orc_fsscs_decode_batch",
-                         "orc_scl_decode", "orc_scl_decode_batch"):
+                         "orc_scl_decode", "orc_scl_decode_batch", "orc_scs_trace",
+                         "orc_fsscs_trace"):
                 getattr(L, name).restype = ctypes.c_int
             del u8p
             _lib = L
@@ -182,6 +191,39 @@ def scs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, 
     _check(lib().orc_scs_decode(mode, int(info.size), _p(info), int(crc_bits), int(D), int(L),
                                 _p(a), _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s)))
     return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
+
+
+def _trace(fn, mode, info_mask, head, llr, cap):
+    info = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    a = _llr_array(mode, llr)
+    u = np.zeros(info.size, np.uint8)
+    st = ctypes.c_uint8(0)
+    pm = ctypes.c_double(0.0)
+    s = _Stats()
+    seq = np.zeros(cap, np.uint32)
+    pl = np.zeros(cap, np.int32)
+    tpm = np.zeros(cap, np.float64)
+    n = fn(mode, int(info.size), _p(info), *head, _p(a), _p(u), ctypes.byref(st),
+           ctypes.byref(pm), ctypes.byref(s), _p(seq), _p(pl), _p(tpm), int(cap))
+    _check(min(n, 0))
+    pops = [(int(seq[q]), int(pl[q]), float(tpm[q])) for q in range(min(n, cap))]
+    return (u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS},
+            pops, n)
+
+
+def scs_trace(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
+              cap: int = 4096):
+    """scs_decode plus the paths taken off the stack in order, as (creation number, length,
+    metric); returns (u_hat, status, pm, stats, pops, number of pops)."""
+    return _trace(lib().orc_scs_trace, mode, info_mask, (int(crc_bits), int(D), int(L)), llr,
+                  cap)
+
+
+def fsscs_trace(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
+                types: int = 0xF, cap: int = 4096):
+    """fsscs_decode plus the paths taken off the stack in order (as scs_trace)."""
+    return _trace(lib().orc_fsscs_trace, mode, info_mask,
+                  (int(crc_bits), int(D), int(L), int(types)), llr, cap)
 
 
 def scs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,

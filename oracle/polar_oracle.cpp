@@ -256,6 +256,23 @@ uint16_t crc16_bits(const uint8_t* bits, int nbits) {
 //    such path is the fallback output; after L failures, or if S empties, decoding
 //    stops with the fallback.
 // ---------------------------------------------------------------------------------
+// Optional record of the paths taken off the stack, in the order they are taken (test
+// instrumentation for the hand-worked traces: it changes no result).
+struct PopTrace {
+  uint32_t* seq = nullptr;
+  int32_t* pl = nullptr;
+  double* pm = nullptr;
+  int cap = 0, n = 0;
+  void add(uint32_t s, int l, double m) {
+    if (n < cap) {
+      seq[n] = s;
+      pl[n] = l;
+      pm[n] = m;
+    }
+    ++n;
+  }
+};
+
 template <class A>
 struct Path {
   typename A::PM pm;
@@ -287,7 +304,8 @@ bool crc_passes(int N, const uint8_t* info, int crc_bits, const uint8_t* u) {
 
 template <class A>
 int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const void* llr,
-                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st) {
+                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st,
+                 PopTrace* tr = nullptr) {
   const int N = 1 << n;
   Tree<A> t;
   t.init(n, llr);
@@ -322,6 +340,7 @@ int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const v
       if (key_less<A>(S[q], S[w])) w = q;
     Path<A> p = S[w];
     S.erase(S.begin() + (long)w);
+    if (tr) tr->add(p.seq, p.pl, (double)p.pm);
 
     if (p.pl == N) {  // termination / CRC, Section 2.2.5
       ++s.completions;
@@ -620,7 +639,7 @@ bool fkey_less(const FPath<A>& a, const FPath<A>& b) {
 template <class A>
 int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int types,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st) {
+                   orc_stats* st, PopTrace* tr = nullptr) {
   const int N = 1 << n;
   std::vector<FNode> sched;
   fssc_nodes(n, 0, info, types, sched);
@@ -656,6 +675,7 @@ int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int t
       if (fkey_less<A>(S[q], S[w])) w = q;
     FPath<A> p = S[w];
     S.erase(S.begin() + (long)w);
+    if (tr) tr->add(p.seq, p.pl, (double)p.pm);
 
     if (p.pl == N) {
       ++s.completions;
@@ -971,6 +991,44 @@ int orc_scs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int 
     case ORC_FIX: return scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
   }
   return -1;
+}
+
+int orc_scs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                  const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap) {
+  const int n = log2_exact(N);
+  if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16) || cap < 0) return -1;
+  PopTrace tr;
+  tr.seq = seq;
+  tr.pl = pl;
+  tr.pm = pm;
+  tr.cap = cap;
+  int rc = -1;
+  switch (mode) {
+    case ORC_F32: rc = scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_F64: rc = scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_FIX: rc = scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
+  }
+  return rc < 0 ? rc : tr.n;
+}
+
+int orc_fsscs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                    int types, const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap) {
+  const int n = log2_exact(N);
+  if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16) || cap < 0) return -1;
+  PopTrace tr;
+  tr.seq = seq;
+  tr.pl = pl;
+  tr.pm = pm;
+  tr.cap = cap;
+  int rc = -1;
+  switch (mode) {
+    case ORC_F32: rc = fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_F64: rc = fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_FIX: rc = fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
+  }
+  return rc < 0 ? rc : tr.n;
 }
 
 int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,

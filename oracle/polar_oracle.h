@@ -99,6 +99,16 @@ int orc_fssc_schedule(int N, const uint8_t* info_mask, int types, int32_t* start
 int orc_node_candidates(int mode, int type, int lam, const double* alpha, double pm,
                         uint8_t* beta_out, double* pm_out, int max_out);
 
+/* As orc_scs_decode / orc_fsscs_decode, and also the paths taken off the stack, in order:
+ * creation number, length and metric of each (the first cap of them).  Returns the number
+ * of paths taken (which may exceed cap), or -1 for bad arguments. */
+int orc_scs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                  const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap);
+int orc_fsscs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
+                    int types, const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
+                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap);
+
 /* FSSCS-RM decoding of one frame (stack rules as orc_scs_decode, one iteration per node). */
 int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                      int types, const void* llr, uint8_t* u_hat, uint8_t* status,
