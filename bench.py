@@ -67,9 +67,10 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: all usable host cores (max 16)")
     ap.add_argument("--wpb", type=int, default=0, choices=(0, 1, 2, 4),
                     help="wavefronts per workgroup (0: the autotuner's choice)")
-    ap.add_argument("--decoder", choices=("scs", "fsscs", "scl"), default="scs",
+    ap.add_argument("--decoder", choices=("scs", "fsscs", "fssc", "scl"), default="scs",
                     help="scs: successive-cancellation stack decoding (the headline); fsscs: "
-                         "fast simplified stack decoding (FSSCS-RM); scl: CA-SCL with a list "
+                         "fast simplified stack decoding (FSSCS-RM); fssc: fast simplified SC "
+                         "(the FSSCS-RM kernel with D = 1, L = 1); scl: CA-SCL with a list "
                          "of L paths; all on the same frames")
     ap.add_argument("--D", type=int, default=D,
                     help="stack depth of the sweep (1..256; the headline is D = 32)")
@@ -83,6 +84,8 @@ def parse():
                     default="sweep",
                     help="sweep: PC(1024,512) headline; mixed: 25 codes / 3 depths in one launch; "
                          "serve: Poisson requests through the continuous-batching server")
+    ap.add_argument("--latency-requests", type=int, default=300,
+                    help="closed-loop requests timed for the latency percentiles of the sweep")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured saturated capacity")
@@ -352,7 +355,9 @@ def main():
             sys.exit(2)
         {"fixed": run_fixed, "depth": run_depth}[args.workload](args)
         return
-    if args.workload == "sweep" and (args.D, args.L) != (D, L):
+    if args.decoder == "fssc":
+        sweep_config(1, 1)  # fast simplified SC: no stack, no second path
+    elif args.workload == "sweep" and (args.D, args.L) != (D, L):
         sweep_config(args.D, args.L)
     if args.gpus != 1:
         print("bench.py: the library decodes on one GPU; --gpus %d is not supported (frames are "
@@ -377,7 +382,7 @@ def main():
     if not args.wpb and args.tune != "off":
         from paper_1809_03606_amd import tune
 
-        dec = args.decoder
+        dec = "fsscs" if args.decoder == "fssc" else args.decoder
         entry = None if args.tune == "force" else tune.apply(ctx, code, D, L, args.dtype, decoder=dec)
         source = "cache"
         if entry is None:
@@ -418,7 +423,8 @@ def main():
     out_st = torch.empty((B,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((B, 8), dtype=torch.int32, device=dev)
 
-    fast = args.decoder == "fsscs"
+    fast = args.decoder in ("fsscs", "fssc")
+    fssc = args.decoder == "fssc"
     scl = args.decoder == "scl"
     if scl:
         def decode_fn(ctx_h, code_h, D_, L_, dt, x, n, p_, s_, st_, strm):
@@ -479,6 +485,23 @@ def main():
     err = binding.scs_ctx_last_error(ctx.handle)
     if err:
         raise RuntimeError("decoder reported %s" % binding.strerror(err))
+
+    # -- request latency: closed-loop requests of 1..256 frames on this code and decoder, one
+    # in flight at a time, host clock from submission to completion (untimed for `value`) --
+    lat_eb = 2.0 if 2.0 in points else points[len(points) // 2]
+    lat_llr = [llr for eb, _, llr in data if eb == lat_eb][0]
+    rng = np.random.default_rng(11)
+    req_ms = []
+    for r in range(args.latency_requests):
+        m = int(rng.integers(1, 257))
+        lo = int(rng.integers(0, B - m + 1))
+        stream.synchronize()
+        t0 = time.perf_counter()
+        decode_fn(ctx.handle, code.handle, D, L, llr_dtype, lat_llr[lo:lo + m], m, out_pay,
+                  out_st, None, stream)
+        stream.synchronize()
+        req_ms.append((time.perf_counter() - t0) * 1e3)
+    req_ms = np.array(req_ms) if req_ms else np.zeros(1)
 
     launch_ms = {eb: [] for eb in points}
     for eb, a, b in ev:
@@ -542,14 +565,15 @@ def main():
 
     line = {
         "metric": "info Mbit/s decoded (N=1024,K=512,D=32) at oracle-matched FER; p99 latency"
-                  + ("; FSSCS-RM decoder" if fast else "; CA-SCL decoder, list %d" % L if scl
-                     else "")
+                  + ("; FSSC decoder" if fssc else "; FSSCS-RM decoder" if fast else
+                     "; CA-SCL decoder, list %d" % L if scl else "")
                   + ("; D=%d, L=%d" % (D, L) if not scl and (D, L) != HEADLINE_DL else ""),
         "value": value, "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
-        "config": {"workload": ("FSSCS-RM" if fast else "CA-SCL" if scl else "SCS")
+        "config": {"workload": ("FSSC" if fssc else "FSSCS-RM" if fast else
+                                "CA-SCL" if scl else "SCS")
                                + (" sweep PC(1024,512)+CRC16 L=%d" % L if scl else
                                   " sweep PC(1024,512)+CRC16 D=%d L=%d" % (D, L))
                                + (" Eb/N0 1.0-3.0 dB" if points == list(POINTS) else
@@ -558,8 +582,13 @@ def main():
                    "ebn0_db": points, "frames_per_point": B, "global_batch": B * len(points),
                    "launches_per_step": len(points), "parallelism": "single GPU",
                    "launch_shape": launch_shape},
-        "latency": {"launch_ms_p50": float(np.percentile(all_ms, 50)),
-                    "launch_ms_p99": float(np.percentile(all_ms, 99))},
+        "latency": {"request_ms_p50": float(np.percentile(req_ms, 50)),
+                    "request_ms_p99": float(np.percentile(req_ms, 99)),
+                    "request": "%d closed-loop requests of 1-256 frames at %.1f dB, one in "
+                               "flight, host clock from submission to completion"
+                               % (args.latency_requests, lat_eb),
+                    "batch_launch_ms_p50": float(np.percentile(all_ms, 50)),
+                    "batch_launch_ms_p99": float(np.percentile(all_ms, 99))},
         "per_point": {str(k): v for k, v in per_point.items()},
         "wall_s": wall, "input_generation_s": gen_s,
         "roofline": roofline,
@@ -621,11 +650,28 @@ def run_mixed(args):
     frames["code"], frames["D"], frames["L"] = cidx, Dv, Lp
     frames["llr_off"], frames["out_off"] = llr_off, out_off
     ctx = binding.ScsContext(0)
+    ctx_plain = binding.ScsContext(0)  # one launch per configuration, library launch shapes
     pay_m = torch.empty(tot_out, dtype=torch.uint8, device=dev)
     st_m = torch.empty(B, dtype=torch.uint8, device=dev)
     pay_p = torch.empty(tot_out, dtype=torch.uint8, device=dev)
     st_p = torch.empty(B, dtype=torch.uint8, device=dev)
     handles = [p.handle for p in pcs]
+    launch_shape = {"waves_per_block": 4, "source": "library default"}
+    if args.wpb:
+        ctx.configure(args.wpb)
+        launch_shape = {"waves_per_block": args.wpb, "source": "flags"}
+    elif args.tune != "off":
+        from paper_1809_03606_amd import tune
+
+        entry = None if args.tune == "force" else tune.apply_mixed(ctx, pcs, frames)
+        source = "cache"
+        if entry is None:
+            t0 = time.time()
+            entry = tune.tune_mixed(ctx, pcs, frames, llr, pay_m, st_m, stream)
+            source = "tuned in %.1f s on %d frames" % (time.time() - t0, entry["frames"])
+        launch_shape = {"waves_per_block": entry["waves_per_block"], "source": source,
+                        "candidates_ms": entry["candidates_ms"]}
+    log("mixed launch shape: %s" % launch_shape)
     binding.scs_mixed_prepare(ctx.handle, handles, frames, stream)
     stream.synchronize()
 
@@ -633,7 +679,7 @@ def run_mixed(args):
         pos = 0
         for (c, d, lo, lo_o, cnt) in groups:
             n, k = codes[c]
-            binding.scs_decode_batch(ctx.handle, pcs[c].handle, d, Lp, binding.SCS_LLR_F32,
+            binding.scs_decode_batch(ctx_plain.handle, pcs[c].handle, d, Lp, binding.SCS_LLR_F32,
                                      llr[lo:].data_ptr(), cnt, pay_p[lo_o:].data_ptr(),
                                      st_p[pos:].data_ptr(), None, stream)
             pos += cnt
@@ -681,7 +727,9 @@ def run_mixed(args):
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded BPSK/AWGN frames generated on the device",
         "config": {"workload": "mixed batch: 25 codes (CRC-16) x D in {8,32,64}, L=8, Eb/N0 U[1.5,3.5]",
-                   "frames": B, "groups": len(groups), "parallelism": "single GPU"},
+                   "frames": B, "groups": len(groups), "parallelism": "single GPU",
+                   "launch_shape": launch_shape},
+        "frames_per_s": B / (np.mean(ms_m) * 1e-3),
         "plain_one_launch_per_config": {"value": v_p, "unit": "Mbit/s", "launches": len(groups),
                                         "ms_per_step": float(np.mean(ms_p))},
         "mixed_over_plain": v_m / v_p,

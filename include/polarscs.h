@@ -64,6 +64,15 @@ typedef struct polar_code polar_code; /* opaque, host-owned, immutable once buil
 int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_db,
                     polar_code** out);
 
+/* Build PC(N, K) from an explicit information set (for example the paper's, taken from the
+ * 3GPP reliability order, Section 5): info_mask holds N bytes, 1 for an information
+ * position and 0 for a frozen one; K is their count and includes crc_bits (0 or 16), whose
+ * bits are the last crc_bits information positions.  Errors: POLAR_EINVAL for N not a
+ * power of two in [2, 2048], a NULL pointer, a mask byte other than 0 / 1, K < 1 or
+ * crc_bits >= K. */
+int polar_construct_set(int32_t N, const uint8_t* info_mask, int32_t crc_bits,
+                        polar_code** out);
+
 /* Read back the parameters; any output pointer may be NULL.  info_mask_or_null, if
  * given, receives N bytes: 1 for an information position, 0 for a frozen one. */
 int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,

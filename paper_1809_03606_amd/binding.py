@@ -24,7 +24,7 @@ NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_CODES = 16 << 20, 64
 SCS_STATUS_OK, SCS_STATUS_FALLBACK, SCS_STATUS_EXHAUSTED = 1, 2, 4
 SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
-EXPORTS = ("polar_construct", "polar_code_query", "polar_code_free", "polar_encode",
+EXPORTS = ("polar_construct", "polar_construct_set", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch",
            "scs_decode_mixed_noalloc", "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
@@ -76,6 +76,7 @@ def lib():
             L = ctypes.CDLL(_LIB_PATH)
             vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
             L.polar_construct.argtypes = [i32, i32, i32, dbl, ctypes.POINTER(vp)]
+            L.polar_construct_set.argtypes = [i32, vp, i32, ctypes.POINTER(vp)]
             L.polar_code_query.argtypes = [vp, vp, vp, vp, vp]
             L.polar_code_free.argtypes = [vp]
             L.polar_code_free.restype = None
@@ -96,7 +97,7 @@ def lib():
             L.scl_decode_batch.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, vp]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
-            for n in ("polar_construct", "polar_code_query", "polar_encode", "polar_encode_device",
+            for n in ("polar_construct", "polar_construct_set", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_decode_mixed_noalloc",
                       "scs_mixed_prepare", "scs_mixed_launch",
@@ -161,6 +162,14 @@ def polar_construct(N: int, K: int, crc_bits: int, design_ebn0_db: float) -> int
     h = ctypes.c_void_p()
     _check(lib().polar_construct(N, K, crc_bits, float(design_ebn0_db), ctypes.byref(h)),
            "polar_construct")
+    return h.value
+
+
+def polar_construct_set(info_mask: np.ndarray, crc_bits: int) -> int:
+    m = np.ascontiguousarray(info_mask, dtype=np.uint8)
+    h = ctypes.c_void_p()
+    _check(lib().polar_construct_set(int(m.size), m.ctypes.data, int(crc_bits), ctypes.byref(h)),
+           "polar_construct_set")
     return h.value
 
 
@@ -280,10 +289,24 @@ def scs_ctx_last_error(ctx: int) -> int:
 class PolarCode:
     """A constructed PC(N, K) (Bhattacharyya set at design_db), CRC bits inside K."""
 
-    def __init__(self, N: int, K: int, crc_bits: int = 0, design_db: float = 2.0):
-        self.handle = polar_construct(N, K, crc_bits, design_db)
+    def __init__(self, N: int, K: int, crc_bits: int = 0, design_db: float = 2.0,
+                 info_mask=None):
+        """info_mask (N bytes, 1 = information position) replaces the construction: the code
+        then has that information set (polar_construct_set) and K must be its size."""
+        if info_mask is None:
+            self.handle = polar_construct(N, K, crc_bits, design_db)
+        else:
+            m = np.asarray(info_mask, dtype=np.uint8)
+            if m.size != N or int(m.sum()) != K:
+                raise ValueError("info_mask must have N = %d entries and K = %d ones" % (N, K))
+            self.handle = polar_construct_set(m, crc_bits)
         self.N, self.K, self.crc_bits, self.info_mask = polar_code_query(self.handle)
         self.design_db = design_db
+
+    @classmethod
+    def from_set(cls, info_mask, crc_bits: int = 0) -> "PolarCode":
+        m = np.asarray(info_mask, dtype=np.uint8)
+        return cls(int(m.size), int(m.sum()), crc_bits, float("nan"), info_mask=m)
 
     @property
     def payload_bits(self) -> int:

@@ -149,3 +149,29 @@ def device_llr_from_noise(torch, codeword, n, ebn0_db: float, rate: float, dtype
     if dtype == "f32":
         return ((2.0 * y) / s2).to(torch.float32)
     return torch.clamp(torch.round(scale * y), -127, 127).to(torch.int8)
+
+
+def _per_frame_sigma(ebn0_db, rate: float):
+    """sigma and sigma^2 of every frame (binary64, host), for per-frame Eb/N0."""
+    s2 = 1.0 / (2.0 * rate * np.power(10.0, np.asarray(ebn0_db, dtype=np.float64) / 10.0))
+    return np.sqrt(s2), s2
+
+
+def bpsk_awgn_llr_per_frame(codeword: np.ndarray, n: np.ndarray, ebn0_db, rate: float) -> np.ndarray:
+    """bpsk_awgn_llr with one Eb/N0 per frame (row)."""
+    s, s2 = _per_frame_sigma(ebn0_db, rate)
+    x = 1.0 - 2.0 * codeword.astype(np.float64)
+    y = x + s[:, None] * n
+    return ((2.0 * y) / s2[:, None]).astype(np.float32)
+
+
+def device_llr_from_noise_per_frame(torch, codeword, n, ebn0_db, rate: float):
+    """bpsk_awgn_llr_per_frame on device tensors, with sigma and sigma^2 computed on the host
+    (so the two agree bit for bit: the device does only IEEE multiply, add and divide)."""
+    s, s2 = _per_frame_sigma(ebn0_db, rate)
+    dev = codeword.device
+    s = torch.from_numpy(s).to(dev)
+    s2 = torch.from_numpy(s2).to(dev)
+    x = 1.0 - 2.0 * codeword.to(torch.float64)
+    y = x + s[:, None] * n
+    return ((2.0 * y) / s2[:, None]).to(torch.float32)

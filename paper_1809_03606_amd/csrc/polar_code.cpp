@@ -151,6 +151,45 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_d
   });
   c->info.assign(N, 0);
   for (int k = 0; k < K; ++k) c->info[order[k]] = 1;
+  polarscs::finish_code(c);
+  *out = c;
+  return POLAR_OK;
+}
+
+int polar_construct_set(int32_t N, const uint8_t* info_mask, int32_t crc_bits,
+                        polar_code** out) {
+  if (!out) return POLAR_EINVAL;
+  *out = nullptr;
+  if (N < 2 || N > 2048 || (N & (N - 1)) != 0 || !info_mask) return POLAR_EINVAL;
+  if (crc_bits != 0 && crc_bits != 16) return POLAR_EINVAL;
+  int K = 0;
+  for (int j = 0; j < N; ++j) {
+    if (info_mask[j] > 1) return POLAR_EINVAL;
+    K += info_mask[j];
+  }
+  if (K < 1 || crc_bits >= K) return POLAR_EINVAL;
+  polar_code* c = new (std::nothrow) polar_code;
+  if (!c) return POLAR_ENOMEM;
+  c->N = N;
+  c->K = K;
+  c->crc = crc_bits;
+  c->logn = 0;
+  while ((1 << c->logn) < N) ++c->logn;
+  c->uid = polarscs::g_next_uid.fetch_add(1);
+  c->info.assign(info_mask, info_mask + N);
+  polarscs::finish_code(c);
+  *out = c;
+  return POLAR_OK;
+}
+
+}  // extern "C"
+
+namespace polarscs {
+
+// Everything a code needs once its information set is chosen: positions, bit words, CRC
+// tables and the fast simplified schedule.
+void finish_code(polar_code* c) {
+  const int N = c->N, K = c->K, crc_bits = c->crc;
   for (int j = 0; j < N; ++j)
     if (c->info[j]) c->info_pos.push_back(j);
   int run = 0;
@@ -190,10 +229,12 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_d
             (uint16_t)(c->crc_syn[(size_t)b * 256 + (v & (v - 1))] ^ (pos < N ? share[pos] : 0));
       }
   }
-  polarscs::build_node_table(c);
-  *out = c;
-  return POLAR_OK;
+  build_node_table(c);
 }
+
+}  // namespace polarscs
+
+extern "C" {
 
 int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,
                      uint8_t* info_mask_or_null) {

@@ -31,4 +31,5 @@ struct polar_code {
 namespace polarscs {
 uint16_t crc16_payload(const uint8_t* bits, int nbits);
 void build_node_table(polar_code* c);
+void finish_code(polar_code* c);
 }

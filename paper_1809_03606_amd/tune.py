@@ -2,7 +2,9 @@
 
 For one (code, D, L, LLR type) it times every launch shape the library offers --
 wavefronts per workgroup (1, 2, 4) -- on a sample batch of noisy frames at a
-representative Eb/N0, and keeps the fastest.  The list decoder packs 8 / L frames into a
+representative Eb/N0, and keeps the fastest.  For a mixed batch (several codes, depths and
+list sizes in one persistent launch) it times the same sizes on a sample of the caller's
+own plan, keyed by the plan's set of configurations.  The list decoder packs 8 / L frames into a
 wavefront at L <= 4 by itself and ignores D.  Results go to a JSON cache keyed by device
 architecture, N, K, CRC bits, D, L and LLR type (default file: $POLARSCS_TUNE_CACHE or
 ~/.cache/polarscs/tune.json), and ``apply`` configures a decoder context from it.  Entries
@@ -138,6 +140,78 @@ def apply(ctx, code, D: int, L: int, dtype: str = "f32", path: str | None = None
     import torch
 
     entry = load(path).get(key(_arch(torch), code, D, L, dtype, decoder))
+    if entry:
+        ctx.configure(entry["waves_per_block"])
+    return entry
+
+
+def mixed_key(arch: str, codes, frames, dtype: str = "f32") -> str:
+    """Cache key of a mixed plan: the sorted set of (N, K, CRC, D, L) configurations it
+    holds (not the frame count or order)."""
+    import hashlib
+
+    import numpy as np
+
+    confs = sorted({(codes[int(c)].N, codes[int(c)].K, codes[int(c)].crc_bits, int(d), int(l))
+                    for c, d, l in np.unique(np.stack([frames["code"], frames["D"],
+                                                       frames["L"]], 1), axis=0)})
+    h = hashlib.sha1(repr(confs).encode()).hexdigest()[:12]
+    return "%s:mixed:%dconf:%s:%s" % (arch, len(confs), h, dtype)
+
+
+def tune_mixed(ctx, codes, frames, llr, payload, status, stream, dtype: str = "f32",
+               sample: int = 262144, reps: int = 2, path: str | None = None,
+               verbose: bool = False) -> dict:
+    """Time the persistent mixed launch (scs_mixed_prepare + scs_mixed_launch) at every
+    workgroup size on the first `sample` descriptors of the caller's plan, over the caller's
+    device buffers (LLRs, payload, status sized for the whole plan); check that every size
+    gives the same bytes; store the fastest under mixed_key and configure ctx with it."""
+    import numpy as np
+    import torch
+
+    sub = np.ascontiguousarray(frames[:sample])
+    handles = [c.handle for c in codes]
+    dt = binding.SCS_LLR_F32 if dtype == "f32" else binding.SCS_LLR_I8
+    binding.scs_mixed_prepare(ctx.handle, handles, sub, stream)
+    stream.synchronize()
+    idx = torch.from_numpy(np.arange(len(sub))).to(status.device)
+    times, ref = {}, None
+    for wpb in CANDIDATES:
+        ctx.configure(wpb)
+        ms = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            binding.scs_mixed_launch(ctx.handle, dt, llr, payload, status, None, stream)
+            b.record(stream)
+            stream.synchronize()
+            if r:
+                ms.append(a.elapsed_time(b))
+        got = (payload.clone(), status[idx].clone())
+        if ref is None:
+            ref = got
+        elif not (torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1])):
+            raise RuntimeError("mixed launch at wpb=%d changed the decoded bits" % wpb)
+        times[str(wpb)] = min(ms)
+        if verbose:
+            print("tune mixed wpb=%d: %.2f ms" % (wpb, min(ms)))
+    best = min(times, key=times.get)
+    entry = {"waves_per_block": int(best), "ms": times[best], "candidates_ms": times,
+             "frames": int(len(sub)), "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    entries = _read(path or cache_path())
+    entries[mixed_key(_arch(torch), codes, frames, dtype)] = entry
+    save(entries, path)
+    ctx.configure(int(best))
+    binding.scs_mixed_prepare(ctx.handle, handles, frames, stream)  # the whole plan again
+    stream.synchronize()
+    return entry
+
+
+def apply_mixed(ctx, codes, frames, dtype: str = "f32", path: str | None = None) -> dict | None:
+    """Configure ctx with the cached workgroup size of this mixed plan, if any."""
+    import torch
+
+    entry = load(path).get(mixed_key(_arch(torch), codes, frames, dtype))
     if entry:
         ctx.configure(entry["waves_per_block"])
     return entry

@@ -165,3 +165,27 @@ def test_scl_rejects_bad_arguments(lib):
     code = binding.PolarCode(64, 32, 0)
     assert lib.scl_decode_batch(None, code.handle, 8, 0, None, 1, None, None, None,
                                 None) == binding.POLAR_EINVAL
+
+
+def test_construct_from_an_explicit_set(lib):
+    """polar_construct_set keeps the given information set; the encoder, CRC placement and
+    schedule follow it exactly as for a constructed code."""
+    rng = np.random.default_rng(5)
+    for N, K, crc in [(2, 1, 0), (4, 3, 0), (32, 17, 16), (256, 100, 16), (2048, 700, 16)]:
+        mask = np.zeros(N, np.uint8)
+        mask[rng.choice(N, K, replace=False)] = 1
+        code = binding.PolarCode.from_set(mask, crc)
+        assert (code.N, code.K, code.crc_bits) == (N, K, crc)
+        assert (code.info_mask == mask).all()
+        pay = channel.payload_bits(23, N, 0, 16, K - crc)
+        assert (code.encode(pay) == oracle.encode_batch(mask, crc, pay)).all()
+        assert binding.polar_code_schedule(code.handle) == [
+            (s, lam, t) for (s, lam, t) in oracle.fssc_schedule(mask)]
+    h = ctypes.c_void_p()
+    ok = np.ones(8, np.uint8)
+    for N, m, crc in [(6, ok, 0), (8, np.zeros(8, np.uint8), 0), (8, ok * 2, 0), (8, ok, 8),
+                      (32, np.r_[np.ones(16, np.uint8), np.zeros(16, np.uint8)], 16)]:
+        m = np.ascontiguousarray(m, dtype=np.uint8)
+        assert lib.polar_construct_set(N, m.ctypes.data, crc, ctypes.byref(h)) == binding.POLAR_EINVAL
+    assert lib.polar_construct_set(8, None, 0, ctypes.byref(h)) == binding.POLAR_EINVAL
+    assert lib.polar_construct_set(8, ok.ctypes.data, 0, None) == binding.POLAR_EINVAL

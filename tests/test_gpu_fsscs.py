@@ -83,3 +83,19 @@ def test_fsscs_deep_stack_matches_oracle_i8(cuda, N, K, crc, D, L, eb):
 def test_fsscs_n1024_crc16_points(cuda, eb):
     """PC(1024,512)+CRC-16, D = 32, L = 8 at three Eb/N0 points, 400 frames each."""
     got, ref, pay = _run(cuda, 1024, 512, 16, 32, 8, eb, 400, seed=int(eb * 10))
+
+
+# FSSC: the fast simplified decoder with D = 1 and L = 1 (Section 2.2.2 nodes on the schedule
+# of Section 3, no stack), at realistic lengths whose schedules hold R-0, R-1, REP and SPC
+# nodes, with and without CRC
+FSSC = [(64, 32, 0, 2.0), (128, 64, 16, 1.5), (256, 128, 0, 2.0), (512, 256, 16, 2.0),
+        (1024, 512, 16, 2.0), (1024, 853, 0, 3.0), (2048, 1024, 16, 2.0), (2048, 512, 0, 1.0)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+@pytest.mark.parametrize("N,K,crc,eb", FSSC)
+def test_fssc_matches_oracle(cuda, N, K, crc, eb, dtype):
+    classes = {t for (_, lam, t) in oracle.fssc_schedule(oracle.construct(N, K, 2.0)) if lam > 0}
+    assert {oracle.NODE_R1, oracle.NODE_REP, oracle.NODE_SPC} <= classes, classes
+    B = 150 if N >= 1024 else 301
+    _run(cuda, N, K, crc, 1, 1, eb, B, seed=91 + N + K, dtype=dtype)

@@ -103,3 +103,78 @@ def test_gpu_full_size_other_decoders_sampled_against_oracle(cuda, decoder):
 def test_gpu_full_size_packed_list_decoder_sampled_against_oracle(cuda, list_size):
     # 8 / L frames share a wavefront; the sample falls anywhere in the packed batch
     _full(cuda, 2.0, "f32", seed=50 + list_size, decoder="scl", list_size=list_size)
+
+
+def test_gpu_mixed_full_batch_sampled_against_oracle(cuda):
+    """The mixed workload at its full size (2 x 10^6 frames over 25 codes x D in {8, 32, 64},
+    L = 8, Eb/N0 uniform in [1.5, 3.5]) in one persistent launch, at the workgroup size the
+    benchmark uses (the tuner's cached choice for this plan, else the library's); a sample
+    of frames is rebuilt on the host with the oracle's encoder and decoded by the oracle."""
+    from paper_1809_03606_amd import binding, tune
+
+    torch = cuda
+    B, Lm, crc, seed = 2_000_000, 8, 16, 4
+    codes = channel.mixed_codes()
+    pcs = [binding.PolarCode(n, k, crc, 2.0) for (n, k) in codes]
+    cidx, Dv, eb = channel.mixed_draw(seed, B)
+    Nf = np.array([codes[c][0] for c in cidx], np.int64)
+    kpf = np.array([codes[c][1] - crc for c in cidx], np.int64)
+    # the LLRs and payloads are laid out grouped by code (descriptors stay in draw order)
+    grouped = np.argsort(cidx, kind="stable")
+    llr_off = np.zeros(B, np.int64)
+    out_off = np.zeros(B, np.int64)
+    llr_off[grouped] = np.concatenate([[0], np.cumsum(Nf[grouped])[:-1]])
+    out_off[grouped] = np.concatenate([[0], np.cumsum(kpf[grouped])[:-1]])
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(B, SAMPLE, replace=False))
+    llr = torch.empty(int(Nf.sum()), dtype=torch.float32, device="cuda")
+    s_pay, s_noise = {}, {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    for c in range(len(codes)):  # frames of one code at a time
+        idx = np.nonzero(cidx == c)[0]
+        n, k = codes[c]
+        for lo in range(0, idx.size, 1 << 16):
+            part = idx[lo:lo + (1 << 16)]
+            pay = channel.device_payload(torch, gen, part.size, k - crc, "cuda")
+            cw = torch.empty((part.size, n), dtype=torch.uint8, device="cuda")
+            pcs[c].encode_device(pay, cw)
+            nz = channel.device_noise(torch, gen, part.size, n, "cuda")
+            x = channel.device_llr_from_noise_per_frame(torch, cw, nz, eb[part], k / n)
+            base = int(llr_off[part[0]])  # frames of one code are contiguous, in order
+            llr[base:base + part.size * n] = x.reshape(-1)
+            hit = np.nonzero(np.isin(part, sample))[0]
+            for j in hit:
+                s_pay[int(part[j])] = pay[j].cpu().numpy()
+                s_noise[int(part[j])] = nz[j].cpu().numpy()
+            del pay, cw, nz, x
+    frames = np.zeros(B, binding.FRAME_DTYPE)
+    frames["code"], frames["D"], frames["L"] = cidx, Dv, Lm
+    frames["llr_off"], frames["out_off"] = llr_off, out_off
+    ctx = binding.ScsContext(0)
+    tune.apply_mixed(ctx, pcs, frames)
+    out = torch.full((int(kpf.sum()),), 0xEE, dtype=torch.uint8, device="cuda")
+    st = torch.full((B,), 0xEE, dtype=torch.uint8, device="cuda")
+    _say("gpu: full-size mixed batch, %d frames in one persistent launch" % B)
+    binding.scs_decode_mixed(ctx.handle, [p.handle for p in pcs], frames, binding.SCS_LLR_F32,
+                             llr, out, st)
+    torch.cuda.synchronize()
+    assert binding.scs_ctx_last_error(ctx.handle) == 0
+    g_st = st.cpu().numpy()
+    assert set(np.unique(g_st)) <= {1, 2, 6}
+    # the sample, rebuilt on the host and decoded by the oracle per (code, D)
+    infos = {}
+    for c, d in sorted({(int(cidx[f]), int(Dv[f])) for f in sample}):
+        sel = [int(f) for f in sample if cidx[f] == c and Dv[f] == d]
+        n, k = codes[c]
+        info = infos.setdefault(c, oracle.construct(n, k, 2.0))
+        cw_h = oracle.encode_batch(info, crc, np.stack([s_pay[f] for f in sel]))
+        h_llr = channel.bpsk_awgn_llr_per_frame(cw_h, np.stack([s_noise[f] for f in sel]),
+                                                eb[sel], k / n)
+        d_llr = np.stack([llr[int(llr_off[f]):int(llr_off[f]) + n].cpu().numpy() for f in sel])
+        assert np.array_equal(h_llr.view(np.uint8), d_llr.view(np.uint8))
+        rp, rs, _ = oracle.scs_decode_batch(oracle.F32, info, crc, d, Lm, h_llr, threads=THREADS)
+        for j, f in enumerate(sel):
+            o = int(out_off[f])
+            got = out[o:o + k - crc].cpu().numpy()
+            assert np.array_equal(got, rp[j]) and g_st[f] == rs[j], (f, c, d)

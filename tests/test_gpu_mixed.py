@@ -180,3 +180,54 @@ def test_gpu_mixed_rejects_bad_descriptors(cuda):
     binding.scs_decode_mixed(ctx.handle, [pc.handle], good, binding.SCS_LLR_F32, x, pay, st)
     cuda.cuda.synchronize()
     assert binding.scs_ctx_last_error(ctx.handle) == 0
+
+
+@pytest.mark.parametrize("wpb", [1, 2, 4])
+def test_gpu_mixed_every_workgroup_size_matches_oracle(cuda, wpb):
+    """Every launch shape the mixed-plan tuner can choose gives the oracle's bits."""
+    from paper_1809_03606_amd import binding
+    from paper_1809_03606_amd.binding import PolarCode
+
+    B = 500
+    codes, frames, flat, per, want, total_out = build_mixed(B, seed=50 + wpb)
+    pcs = [PolarCode(N, K, 16, 2.0) for (N, K) in codes]
+    ctx = binding.ScsContext(0, wpb)
+    _say("gpu: mixed batch at %d wavefronts per workgroup" % wpb)
+    pay, st, stats = _gpu_mixed(cuda, [p.handle for p in pcs], frames, flat, total_out, ctx=ctx)
+    for f in range(B):
+        c = frames["code"][f]
+        kp = codes[c][1] - 16
+        o = frames["out_off"][f]
+        assert (pay[o:o + kp] == want[f][0]).all() and st[f] == want[f][1], (wpb, f)
+
+
+def test_gpu_mixed_plan_tuner(cuda, tmp_path):
+    """tune_mixed times the persistent launch at every workgroup size on the caller's plan,
+    checks the bytes agree, stores the fastest under the plan's key and applies it."""
+    from paper_1809_03606_amd import binding, tune
+    from paper_1809_03606_amd.binding import PolarCode
+
+    B = 2000
+    codes, frames, flat, per, want, total_out = build_mixed(B, seed=57)
+    pcs = [PolarCode(N, K, 16, 2.0) for (N, K) in codes]
+    ctx = binding.ScsContext(0)
+    x = cuda.from_numpy(flat).cuda()
+    pay = cuda.zeros((total_out,), dtype=cuda.uint8, device="cuda")
+    st = cuda.zeros((B,), dtype=cuda.uint8, device="cuda")
+    stream = cuda.cuda.Stream()
+    path = str(tmp_path / "tune.json")
+    _say("gpu: mixed plan tuner on %d frames" % B)
+    entry = tune.tune_mixed(ctx, pcs, frames, x, pay, st, stream, path=path)
+    assert set(entry["candidates_ms"]) == {"1", "2", "4"}
+    assert entry["waves_per_block"] in (1, 2, 4)
+    got = tune.apply_mixed(binding.ScsContext(0), pcs, frames, path=path)
+    assert got["waves_per_block"] == entry["waves_per_block"]
+    # the context is left with the whole plan prepared at the chosen size
+    binding.scs_mixed_launch(ctx.handle, binding.SCS_LLR_F32, x, pay, st, None, stream)
+    stream.synchronize()
+    p, s = pay.cpu().numpy(), st.cpu().numpy()
+    for f in range(B):
+        c = frames["code"][f]
+        kp = codes[c][1] - 16
+        o = frames["out_off"][f]
+        assert (p[o:o + kp] == want[f][0]).all() and s[f] == want[f][1], f
