@@ -176,7 +176,12 @@ int scs_decode_mixed(scs_ctx* ctx, const polar_code* const* codes, int32_t n_cod
  * launch enqueues the decoding of the prepared plan and neither allocates, copies nor
  * sets memory from the host, so a caller can capture it in a HIP graph and replay it while
  * the plan and the buffers stay the same.  The codes passed to prepare must outlive the
- * last launch of that plan. */
+ * last launch of that plan.
+ * Streams: a context holds one plan and one work counter.  Outside graph capture the
+ * context orders its own mixed calls whatever streams they use: prepare and launch make
+ * their stream wait (on the device) for the context's previous launch.  Launches captured
+ * into a graph are not tracked: their replays must be ordered against the context's other
+ * mixed calls by the caller (one stream, or events).  Contexts are independent. */
 int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_codes,
                       const scs_frame* frames_host, int64_t n_frames, void* hip_stream);
 int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8_t* payload_dev,

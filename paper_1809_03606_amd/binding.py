@@ -205,6 +205,7 @@ def scs_ctx_create(device: int = 0) -> int:
 
 
 def scs_ctx_destroy(ctx: int):
+    _PLANS.pop(ctx, None)
     lib().scs_ctx_destroy(ctx)
 
 
@@ -237,10 +238,57 @@ def polar_code_schedule(handle: int) -> list:
     return [(int(j), int(v) & 15, int(v) >> 4) for j, v in enumerate(raw) if v != 0xFF]
 
 
+_PLANS = {}  # context handle -> extent of its prepared mixed plan (see _plan_extent)
+
+
+def _plan_extent(codes, fr):
+    """(LLR elements, payload bytes, frames) that the buffers of a mixed plan must hold, or
+    None when a descriptor names no code (the library refuses such a plan itself)."""
+    n = int(fr.shape[0])
+    if n == 0:
+        return (0, 0, 0)
+    shapes = []
+    for h in codes:
+        N, K, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().polar_code_query(h, ctypes.byref(N), ctypes.byref(K), ctypes.byref(r), None),
+               "polar_code_query")
+        shapes.append((N.value, K.value - r.value))
+    c = fr["code"].astype(np.int64)
+    if len(shapes) == 0 or c.min() < 0 or c.max() >= len(shapes):
+        return None
+    Ns = np.array([a for a, _ in shapes], np.int64)[c]
+    kps = np.array([b for _, b in shapes], np.int64)[c]
+    return int((fr["llr_off"] + Ns).max()), int((fr["out_off"] + kps).max()), n
+
+
+def _check_plan_buffers(extent, llr_dtype, llr_dev, payload_dev, status_dev, stats_dev):
+    """Check torch tensors against a plan's extent (raw addresses cannot be checked)."""
+    if extent is None:
+        return
+    need_llr, need_out, n = extent
+    import torch
+
+    def tensor(t):
+        return t is not None and not isinstance(t, int) and hasattr(t, "is_cuda")
+
+    if tensor(llr_dev):
+        _device_buffer(llr_dev, "llr", (torch.float32,) if llr_dtype == SCS_LLR_F32 else
+                       (torch.int8,), need_llr, None)
+    dev = llr_dev.device.index if tensor(llr_dev) else None
+    if tensor(payload_dev):
+        _device_buffer(payload_dev, "payload", (torch.uint8,), need_out, dev)
+    if tensor(status_dev):
+        _device_buffer(status_dev, "status", (torch.uint8,), n, dev)
+    if tensor(stats_dev):
+        _device_buffer(stats_dev, "stats", (torch.int32, torch.uint32), n * len(STATS_FIELDS), dev)
+
+
 def scs_decode_mixed(ctx: int, codes, frames: np.ndarray, llr_dtype: int, llr_dev, payload_dev,
                      status_dev, stats_dev=None, stream=None):
     arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
     fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    _check_plan_buffers(_plan_extent(codes, fr), llr_dtype, llr_dev, payload_dev, status_dev,
+                        stats_dev)
     _check(lib().scs_decode_mixed(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
                                   fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
                                   _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
@@ -253,6 +301,8 @@ def scs_decode_mixed_noalloc(ctx: int, codes, frames: np.ndarray, llr_dtype: int
     (no device allocation); raises PolarError(POLAR_ETOOLARGE) beyond its capacity."""
     arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
     fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    _check_plan_buffers(_plan_extent(codes, fr), llr_dtype, llr_dev, payload_dev, status_dev,
+                        stats_dev)
     _check(lib().scs_decode_mixed_noalloc(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
                                           fr.ctypes.data, int(fr.shape[0]), int(llr_dtype),
                                           _addr(llr_dev), _addr(payload_dev), _addr(status_dev),
@@ -263,13 +313,17 @@ def scs_decode_mixed_noalloc(ctx: int, codes, frames: np.ndarray, llr_dtype: int
 def scs_mixed_prepare(ctx: int, codes, frames: np.ndarray, stream=None):
     arr = (ctypes.c_void_p * max(1, len(codes)))(*codes)
     fr = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    extent = _plan_extent(codes, fr)
     _check(lib().scs_mixed_prepare(ctx, ctypes.cast(arr, ctypes.c_void_p), len(codes),
                                    fr.ctypes.data, int(fr.shape[0]), _stream(stream)),
            "scs_mixed_prepare")
+    _PLANS[ctx] = extent
 
 
 def scs_mixed_launch(ctx: int, llr_dtype: int, llr_dev, payload_dev, status_dev, stats_dev=None,
                      stream=None):
+    """Launch the plan last prepared on ctx; torch tensors are checked against that plan."""
+    _check_plan_buffers(_PLANS.get(ctx), llr_dtype, llr_dev, payload_dev, status_dev, stats_dev)
     _check(lib().scs_mixed_launch(ctx, int(llr_dtype), _addr(llr_dev), _addr(payload_dev),
                                   _addr(status_dev), _addr(stats_dev), _stream(stream)),
            "scs_mixed_launch")

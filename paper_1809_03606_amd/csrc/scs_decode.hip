@@ -544,6 +544,7 @@ struct scs_ctx {
   char* h_stage = nullptr;
   size_t cap_stage = 0;
   hipEvent_t staged = nullptr;
+  hipEvent_t launched = nullptr;  // the last mixed launch enqueued outside graph capture
   uint32_t plan_frames = 0;
   int plan_wave_words = 0;
   void* scratch = nullptr;  // device address of this device's fixed scratch array
@@ -594,9 +595,11 @@ int scs_ctx_create(int device, scs_ctx** out) {
       hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipMalloc(&c->d_counter, sizeof(uint32_t)) != hipSuccess ||
       hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->launched, hipEventDisableTiming) != hipSuccess ||
       resolve_scratch(device, &c->scratch) != POLAR_OK) {
     (void)hipFree(c->d_counter);
     if (c->staged) (void)hipEventDestroy(c->staged);
+    if (c->launched) (void)hipEventDestroy(c->launched);
     delete c;
     (void)hipSetDevice(dev0);
     return POLAR_EDEVICE;
@@ -617,6 +620,7 @@ void scs_ctx_destroy(scs_ctx* ctx) {
   (void)hipFree(ctx->d_counter);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+  if (ctx->launched) (void)hipEventDestroy(ctx->launched);
   delete ctx;
 }
 
@@ -818,6 +822,8 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
   }
   const size_t bytes = nc * sizeof(CodeArgs) + nf * sizeof(scs_frame) + nf * sizeof(int32_t);
   if (hipEventSynchronize(ctx->staged) != hipSuccess) return POLAR_EDEVICE;  // staging free
+  // the plan buffers may still be read by this context's last launch, on any stream
+  if (hipStreamWaitEvent(s, ctx->launched, 0) != hipSuccess) return POLAR_EDEVICE;
   if (bytes > ctx->cap_stage) {
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     ctx->h_stage = nullptr;
@@ -870,6 +876,12 @@ int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8
     per_cu = 1;
   const int64_t need = ((int64_t)ctx->plan_frames + wpb - 1) / wpb;
   const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, need);
+  // Launches of one context share its work counter: outside graph capture, a launch waits
+  // for the context's previous one (on any stream) and is recorded for the next.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return POLAR_EDEVICE;
+  const bool track = cap == hipStreamCaptureStatusNone;
+  if (track && hipStreamWaitEvent(s, ctx->launched, 0) != hipSuccess) return POLAR_EDEVICE;
   clear_stale_error();
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, ctx->d_counter);
   if (llr_dtype == SCS_LLR_F32) {
@@ -883,7 +895,7 @@ int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8
                        ctx->d_order, ctx->plan_frames, (const int8_t*)llr_dev, payload_dev,
                        status_dev, stats_dev, ctx->d_counter, ww);
   }
-  if (hipGetLastError() != hipSuccess) {
+  if (hipGetLastError() != hipSuccess || (track && hipEventRecord(ctx->launched, s) != hipSuccess)) {
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->last_error = POLAR_EDEVICE;
     return POLAR_EDEVICE;

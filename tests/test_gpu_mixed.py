@@ -231,3 +231,33 @@ def test_gpu_mixed_plan_tuner(cuda, tmp_path):
         kp = codes[c][1] - 16
         o = frames["out_off"][f]
         assert (p[o:o + kp] == want[f][0]).all() and s[f] == want[f][1], f
+
+
+def test_gpu_mixed_one_context_two_streams(cuda):
+    """Two different plans decoded on one context from two streams with no host
+    synchronisation in between: the context orders its own calls, both results are exact."""
+    from paper_1809_03606_amd import binding
+    from paper_1809_03606_amd.binding import PolarCode
+
+    runs = []
+    for seed, B in ((71, 700), (72, 300)):
+        codes, frames, flat, per, want, total_out = build_mixed(B, seed=seed)
+        runs.append((codes, frames, cuda.from_numpy(flat).cuda(), want, total_out))
+    pcs = [PolarCode(N, K, 16, 2.0) for (N, K) in runs[0][0]]
+    ctx = binding.ScsContext(0)
+    streams = [cuda.cuda.Stream(), cuda.cuda.Stream()]
+    outs = [(cuda.full((r[4],), 0xEE, dtype=cuda.uint8, device="cuda"),
+             cuda.full((len(r[1]),), 0xEE, dtype=cuda.uint8, device="cuda")) for r in runs]
+    cuda.cuda.synchronize()
+    _say("gpu: two mixed plans on one context, two streams")
+    for (codes, frames, x, want, total_out), s, (pay, st) in zip(runs, streams, outs):
+        binding.scs_decode_mixed(ctx.handle, [p.handle for p in pcs], frames,
+                                 binding.SCS_LLR_F32, x, pay, st, None, s)
+    cuda.cuda.synchronize()
+    for (codes, frames, x, want, total_out), (pay, st) in zip(runs, outs):
+        p, s_ = pay.cpu().numpy(), st.cpu().numpy()
+        for f in range(len(frames)):
+            kp = codes[frames["code"][f]][1] - 16
+            o = frames["out_off"][f]
+            assert (p[o:o + kp] == want[f][0]).all() and s_[f] == want[f][1], f
+    assert binding.scs_ctx_last_error(ctx.handle) == 0
