@@ -71,34 +71,39 @@ def lib():
             L.orc_leaf_llr.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int]
             L.orc_leaf_llr.restype = ctypes.c_double
             L.orc_scs_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, vp, vp, vp, vp, vp]
+                                         ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int]
             L.orc_scs_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                                ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64,
-                                               vp, vp, vp]
+                                               vp, vp, vp, ctypes.c_int]
+            L.orc_encode_systematic_batch.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp,
+                                                      ctypes.c_int64, vp]
             L.orc_ml_decode.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int64]
             L.orc_fssc_schedule.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
             L.orc_node_candidates.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                               ctypes.c_double, vp, vp, ctypes.c_int]
             L.orc_fsscs_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+                                           ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp,
+                                           ctypes.c_int]
             L.orc_fsscs_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
-                                                 ctypes.c_int64, vp, vp, vp]
+                                                 ctypes.c_int64, vp, vp, vp, ctypes.c_int]
             L.orc_scs_trace.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+                                        ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int,
+                                        ctypes.c_int]
             L.orc_fsscs_trace.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
-                                          vp, vp, vp, vp, vp, ctypes.c_int]
+                                          vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]
             L.orc_scl_decode.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
-                                         vp, vp, vp, vp, vp]
+                                         vp, vp, vp, vp, vp, ctypes.c_int]
             L.orc_scl_decode_batch.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
-                                               ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp]
+                                               ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
+                                               ctypes.c_int]
             for name in ("orc_construct", "orc_bhattacharyya_log", "orc_polar_transform",
                          "orc_encode_batch", "orc_sc_decode", "orc_scs_decode",
                          "orc_scs_decode_batch", "orc_ml_decode", "orc_fssc_schedule",
                          "orc_node_candidates", "orc_fsscs_decode", "orc_fsscs_decode_batch",
                          "orc_scl_decode", "orc_scl_decode_batch", "orc_scs_trace",
-                         "orc_fsscs_trace"):
+                         "orc_fsscs_trace", "orc_encode_systematic_batch"):
                 getattr(L, name).restype = ctypes.c_int
             del u8p
             _lib = L
@@ -149,12 +154,17 @@ def polar_transform(u) -> np.ndarray:
     return c
 
 
-def encode_batch(info_mask: np.ndarray, crc_bits: int, payload: np.ndarray) -> np.ndarray:
+def encode_batch(info_mask: np.ndarray, crc_bits: int, payload: np.ndarray,
+                 systematic: bool = False) -> np.ndarray:
+    """Codewords of B payloads (CRC appended): u F^(x)n with the message at the information
+    positions of u, or with systematic=True the codeword that shows the message at the
+    information positions (Section 2.2.2, last paragraph; Section 4)."""
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     pay = np.ascontiguousarray(payload, dtype=np.uint8)
     B = pay.shape[0]
     cw = np.zeros((B, info.size), np.uint8)
-    _check(lib().orc_encode_batch(int(info.size), _p(info), int(crc_bits), _p(pay), B, _p(cw)))
+    fn = lib().orc_encode_systematic_batch if systematic else lib().orc_encode_batch
+    _check(fn(int(info.size), _p(info), int(crc_bits), _p(pay), B, _p(cw)))
     return cw
 
 
@@ -178,7 +188,8 @@ def leaf_llr(mode: int, llr, prefix, i: int) -> float:
     return float(lib().orc_leaf_llr(mode, int(a.size), _p(a), _p(pre), int(i)))
 
 
-def scs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr):
+def scs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
+               systematic: bool = False):
     """SCS decoding of one frame (Section 2.2.5 with Section 3.3's reduced memory).
 
     Returns (u_hat[N], status, path_metric, stats dict)."""
@@ -189,11 +200,12 @@ def scs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, 
     pm = ctypes.c_double(0.0)
     s = _Stats()
     _check(lib().orc_scs_decode(mode, int(info.size), _p(info), int(crc_bits), int(D), int(L),
-                                _p(a), _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s)))
+                                _p(a), _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s),
+                                int(bool(systematic))))
     return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
 
 
-def _trace(fn, mode, info_mask, head, llr, cap):
+def _trace(fn, mode, info_mask, head, llr, cap, systematic=False):
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     a = _llr_array(mode, llr)
     u = np.zeros(info.size, np.uint8)
@@ -204,7 +216,8 @@ def _trace(fn, mode, info_mask, head, llr, cap):
     pl = np.zeros(cap, np.int32)
     tpm = np.zeros(cap, np.float64)
     n = fn(mode, int(info.size), _p(info), *head, _p(a), _p(u), ctypes.byref(st),
-           ctypes.byref(pm), ctypes.byref(s), _p(seq), _p(pl), _p(tpm), int(cap))
+           ctypes.byref(pm), ctypes.byref(s), _p(seq), _p(pl), _p(tpm), int(cap),
+           int(bool(systematic)))
     _check(min(n, 0))
     pops = [(int(seq[q]), int(pl[q]), float(tpm[q])) for q in range(min(n, cap))]
     return (u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS},
@@ -212,22 +225,22 @@ def _trace(fn, mode, info_mask, head, llr, cap):
 
 
 def scs_trace(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
-              cap: int = 4096):
+              cap: int = 4096, systematic: bool = False):
     """scs_decode plus the paths taken off the stack in order, as (creation number, length,
     metric); returns (u_hat, status, pm, stats, pops, number of pops)."""
     return _trace(lib().orc_scs_trace, mode, info_mask, (int(crc_bits), int(D), int(L)), llr,
-                  cap)
+                  cap, systematic)
 
 
 def fsscs_trace(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
-                types: int = 0xF, cap: int = 4096):
+                types: int = 0xF, cap: int = 4096, systematic: bool = False):
     """fsscs_decode plus the paths taken off the stack in order (as scs_trace)."""
     return _trace(lib().orc_fsscs_trace, mode, info_mask,
-                  (int(crc_bits), int(D), int(L), int(types)), llr, cap)
+                  (int(crc_bits), int(D), int(L), int(types)), llr, cap, systematic)
 
 
 def scs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
-                     threads: int = 1):
+                     threads: int = 1, systematic: bool = False):
     """Decode frames llr[B][N]; returns (payload[B][K-r], status[B], stats[B]).
 
     With threads > 1 the frames are split into contiguous chunks decoded concurrently
@@ -248,7 +261,7 @@ def scs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L:
             return 0
         return L_.orc_scs_decode_batch(mode, N, _p(info), int(crc_bits), int(D), int(L),
                                        _p(a[lo:hi]), hi - lo, _p(pay[lo:hi]), _p(status[lo:hi]),
-                                       _p(stats[lo:hi]))
+                                       _p(stats[lo:hi]), int(bool(systematic)))
 
     threads = max(1, min(int(threads), B if B else 1))
     if threads == 1:
@@ -289,7 +302,7 @@ def node_candidates(mode: int, node_type: int, alpha, pm: float = 0.0):
 
 
 def fsscs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
-                 types: int = TYPES_ALL):
+                 types: int = TYPES_ALL, systematic: bool = False):
     """FSSCS-RM decoding of one frame (Section 4).  Returns (u_hat, status, pm, stats)."""
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     a = _llr_array(mode, llr)
@@ -299,12 +312,12 @@ def fsscs_decode(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int
     s = _Stats()
     _check(lib().orc_fsscs_decode(mode, int(info.size), _p(info), int(crc_bits), int(D), int(L),
                                   int(types), _p(a), _p(u), ctypes.byref(st), ctypes.byref(pm),
-                                  ctypes.byref(s)))
+                                  ctypes.byref(s), int(bool(systematic))))
     return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
 
 
 def fsscs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, L: int, llr,
-                       threads: int = 1, types: int = TYPES_ALL):
+                       threads: int = 1, types: int = TYPES_ALL, systematic: bool = False):
     """Decode frames llr[B][N] with FSSCS-RM; returns (payload[B][K-r], status[B], stats[B])."""
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     a = _llr_array(mode, llr)
@@ -322,7 +335,8 @@ def fsscs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, 
             return 0
         return L_.orc_fsscs_decode_batch(mode, N, _p(info), int(crc_bits), int(D), int(L),
                                          int(types), _p(a[lo:hi]), hi - lo, _p(pay[lo:hi]),
-                                         _p(status[lo:hi]), _p(stats[lo:hi]))
+                                         _p(status[lo:hi]), _p(stats[lo:hi]),
+                                         int(bool(systematic)))
 
     threads = max(1, min(int(threads), B if B else 1))
     if threads == 1:
@@ -335,7 +349,8 @@ def fsscs_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, D: int, 
     return pay, status, stats
 
 
-def scl_decode(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr):
+def scl_decode(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr,
+               systematic: bool = False):
     """CA-SCL decoding of one frame (Section 2.2.3).  Returns (u_hat, status, pm, stats)."""
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     a = _llr_array(mode, llr)
@@ -344,12 +359,13 @@ def scl_decode(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr):
     pm = ctypes.c_double(0.0)
     s = _Stats()
     _check(lib().orc_scl_decode(mode, int(info.size), _p(info), int(crc_bits), int(L), _p(a),
-                                _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s)))
+                                _p(u), ctypes.byref(st), ctypes.byref(pm), ctypes.byref(s),
+                                int(bool(systematic))))
     return u, int(st.value), float(pm.value), {f: int(getattr(s, f)) for f in STATS_FIELDS}
 
 
 def scl_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, llr,
-                     threads: int = 1):
+                     threads: int = 1, systematic: bool = False):
     """Decode frames llr[B][N] with CA-SCL; returns (payload[B][K-r], status[B], stats[B])."""
     info = np.ascontiguousarray(info_mask, dtype=np.uint8)
     a = _llr_array(mode, llr)
@@ -367,7 +383,7 @@ def scl_decode_batch(mode: int, info_mask: np.ndarray, crc_bits: int, L: int, ll
             return 0
         return L_.orc_scl_decode_batch(mode, N, _p(info), int(crc_bits), int(L), _p(a[lo:hi]),
                                        hi - lo, _p(pay[lo:hi]), _p(status[lo:hi]),
-                                       _p(stats[lo:hi]))
+                                       _p(stats[lo:hi]), int(bool(systematic)))
 
     threads = max(1, min(int(threads), B if B else 1))
     if threads == 1:

@@ -302,9 +302,19 @@ bool crc_passes(int N, const uint8_t* info, int crc_bits, const uint8_t* u) {
   return true;
 }
 
+// CRC check of a decided bit vector u.  With systematic encoding (Section 2.2.2, last
+// paragraph; Section 4) the message sits in the codeword estimate x = u F^(x)n at the
+// information positions, so the check reads x there; otherwise it reads u.
+bool path_crc_passes(int N, const uint8_t* info, int crc_bits, const uint8_t* u, bool sys) {
+  if (!sys) return crc_passes(N, info, crc_bits, u);
+  std::vector<uint8_t> x((size_t)N);
+  orc_polar_transform(N, u, x.data());
+  return crc_passes(N, info, crc_bits, x.data());
+}
+
 template <class A>
 int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const void* llr,
-                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st,
+                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st, bool sys,
                  PopTrace* tr = nullptr) {
   const int N = 1 << n;
   Tree<A> t;
@@ -344,7 +354,7 @@ int scs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, const v
 
     if (p.pl == N) {  // termination / CRC, Section 2.2.5
       ++s.completions;
-      if (crc_passes(N, info, crc_bits, p.u.data())) {
+      if (path_crc_passes(N, info, crc_bits, p.u.data(), sys)) {
         result = p;
         out = &result;
         stat = ORC_ST_OK;
@@ -639,7 +649,7 @@ bool fkey_less(const FPath<A>& a, const FPath<A>& b) {
 template <class A>
 int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int types,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st, PopTrace* tr = nullptr) {
+                   orc_stats* st, bool sys, PopTrace* tr = nullptr) {
   const int N = 1 << n;
   std::vector<FNode> sched;
   fssc_nodes(n, 0, info, types, sched);
@@ -680,8 +690,10 @@ int fsscs_decode_t(int n, const uint8_t* info, int crc_bits, int D, int L, int t
     if (p.pl == N) {
       ++s.completions;
       std::vector<uint8_t> u(N);
-      orc_polar_transform(N, p.beta.data(), u.data());  // re-encode the codeword estimate
-      if (crc_passes(N, info, crc_bits, u.data())) {
+      // systematic: the message is read from the codeword estimate (beta) itself;
+      // otherwise from its re-encoding u
+      orc_polar_transform(N, p.beta.data(), u.data());
+      if (crc_passes(N, info, crc_bits, sys ? p.beta.data() : u.data())) {
         result = p;
         out = &result;
         stat = ORC_ST_OK;
@@ -791,7 +803,8 @@ struct ListPath {
 
 template <class A>
 int scl_decode_t(int n, const uint8_t* info, int crc_bits, int L, const void* llr,
-                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st) {
+                 uint8_t* u_hat, uint8_t* status, double* pm_out, orc_stats* st,
+                 bool sys) {
   typedef typename A::PM PM;
   const int N = 1 << n;
   orc_stats s;
@@ -852,7 +865,7 @@ int scl_decode_t(int n, const uint8_t* info, int crc_bits, int L, const void* ll
     stat = ORC_ST_FALLBACK;
     for (size_t q : order) {
       ++s.completions;
-      if (crc_passes(N, info, crc_bits, list[q].u.data())) {
+      if (path_crc_passes(N, info, crc_bits, list[q].u.data(), sys)) {
         out = q;
         stat = ORC_ST_OK;
         break;
@@ -957,6 +970,39 @@ int orc_encode_batch(int N, const uint8_t* info_mask, int crc_bits, const uint8_
   return 0;
 }
 
+int orc_encode_systematic_batch(int N, const uint8_t* info_mask, int crc_bits,
+                                const uint8_t* payload, int64_t B, uint8_t* codeword) {
+  // Systematic encoding (Section 2.2.2, last paragraph; Section 4): the codeword carries the
+  // message itself at the information positions.  Two passes of the transform: put the
+  // message at the information positions of v, take u = v F^(x)n, clear u at the frozen
+  // positions, and send x = u F^(x)n.  x is a codeword of the code (u is zero where frozen)
+  // and shows the message at the information positions when the set is closed under the
+  // binary-domination order, as the constructed sets are.
+  if (log2_exact(N) < 0 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  std::vector<int> pos;
+  for (int j = 0; j < N; ++j)
+    if (info_mask[j]) pos.push_back(j);
+  const int K = (int)pos.size();
+  const int k = K - crc_bits;
+  if (k < 0) return -1;
+  std::vector<uint8_t> msg((size_t)K), v((size_t)N), u((size_t)N);
+  for (int64_t b = 0; b < B; ++b) {
+    // the message: payload, then its CRC remainder (most significant bit first)
+    for (int j = 0; j < k; ++j) msg[j] = payload[b * k + j] & 1;
+    if (crc_bits) {
+      const uint16_t c = crc16_bits(msg.data(), k);
+      for (int j = 0; j < crc_bits; ++j) msg[k + j] = (uint8_t)((c >> (crc_bits - 1 - j)) & 1);
+    }
+    std::fill(v.begin(), v.end(), 0);
+    for (int j = 0; j < K; ++j) v[pos[j]] = msg[j];
+    orc_polar_transform(N, v.data(), u.data());
+    for (int j = 0; j < N; ++j)
+      if (!info_mask[j]) u[j] = 0;
+    orc_polar_transform(N, u.data(), codeword + b * N);
+  }
+  return 0;
+}
+
 int orc_sc_decode(int mode, int N, const uint8_t* info_mask, const void* llr, uint8_t* u_hat,
                   double* leaf_llr) {
   const int n = log2_exact(N);
@@ -982,20 +1028,22 @@ double orc_leaf_llr(int mode, int N, const void* llr, const uint8_t* prefix, int
 
 int orc_scs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st) {
+                   orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  const bool sys = systematic != 0;
   switch (mode) {
-    case ORC_F32: return scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
-    case ORC_F64: return scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
-    case ORC_FIX: return scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st);
+    case ORC_F32: return scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, sys);
+    case ORC_F64: return scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, sys);
+    case ORC_FIX: return scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, sys);
   }
   return -1;
 }
 
 int orc_scs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap) {
+                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap,
+                  int systematic) {
   const int n = log2_exact(N);
   if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16) || cap < 0) return -1;
   PopTrace tr;
@@ -1005,16 +1053,17 @@ int orc_scs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D
   tr.cap = cap;
   int rc = -1;
   switch (mode) {
-    case ORC_F32: rc = scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
-    case ORC_F64: rc = scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
-    case ORC_FIX: rc = scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_F32: rc = scs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
+    case ORC_F64: rc = scs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
+    case ORC_FIX: rc = scs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
   }
   return rc < 0 ? rc : tr.n;
 }
 
 int orc_fsscs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                     int types, const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap) {
+                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap,
+                    int systematic) {
   const int n = log2_exact(N);
   if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16) || cap < 0) return -1;
   PopTrace tr;
@@ -1024,16 +1073,16 @@ int orc_fsscs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int
   tr.cap = cap;
   int rc = -1;
   switch (mode) {
-    case ORC_F32: rc = fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
-    case ORC_F64: rc = fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
-    case ORC_FIX: rc = fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, &tr); break;
+    case ORC_F32: rc = fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
+    case ORC_F64: rc = fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
+    case ORC_FIX: rc = fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, systematic != 0, &tr); break;
   }
   return rc < 0 ? rc : tr.n;
 }
 
 int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                          const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
-                         orc_stats* st) {
+                         orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0) return -1;
   const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
@@ -1044,8 +1093,14 @@ int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits
   for (int64_t b = 0; b < B; ++b) {
     int rc = orc_scs_decode(mode, N, info_mask, crc_bits, D, L,
                             (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
-                            nullptr, st ? st + b : nullptr);
+                            nullptr, st ? st + b : nullptr, systematic);
     if (rc) return rc;
+    // the payload: the first K - crc information bits of u, or with systematic encoding of
+    // the codeword estimate u F^(x)n
+    if (systematic) {
+      std::vector<uint8_t> x(u);
+      orc_polar_transform(N, x.data(), u.data());
+    }
     int q = 0;
     for (int j = 0; j < N && q < k; ++j)
       if (info_mask[j]) payload[b * k + q++] = u[j];
@@ -1129,20 +1184,21 @@ int orc_node_candidates(int mode, int type, int lam, const double* alpha, double
 
 int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                      int types, const void* llr, uint8_t* u_hat, uint8_t* status,
-                     double* pm_out, orc_stats* st) {
+                     double* pm_out, orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0 || D < 1 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  const bool sys = systematic != 0;
   switch (mode) {
-    case ORC_F32: return fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
-    case ORC_F64: return fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
-    case ORC_FIX: return fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st);
+    case ORC_F32: return fsscs_decode_t<ArF32>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, sys);
+    case ORC_F64: return fsscs_decode_t<ArF64>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, sys);
+    case ORC_FIX: return fsscs_decode_t<ArFix>(n, info_mask, crc_bits, D, L, types, llr, u_hat, status, pm_out, st, sys);
   }
   return -1;
 }
 
 int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
                            int L, int types, const void* llr, int64_t B, uint8_t* payload,
-                           uint8_t* status, orc_stats* st) {
+                           uint8_t* status, orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0) return -1;
   const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
@@ -1153,8 +1209,14 @@ int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bi
   for (int64_t b = 0; b < B; ++b) {
     int rc = orc_fsscs_decode(mode, N, info_mask, crc_bits, D, L, types,
                               (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
-                              nullptr, st ? st + b : nullptr);
+                              nullptr, st ? st + b : nullptr, systematic);
     if (rc) return rc;
+    // the payload: the first K - crc information bits of u, or with systematic encoding of
+    // the codeword estimate u F^(x)n
+    if (systematic) {
+      std::vector<uint8_t> x(u);
+      orc_polar_transform(N, x.data(), u.data());
+    }
     int q = 0;
     for (int j = 0; j < N && q < k; ++j)
       if (info_mask[j]) payload[b * k + q++] = u[j];
@@ -1164,20 +1226,21 @@ int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bi
 
 int orc_scl_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st) {
+                   orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0 || L < 1 || (crc_bits != 0 && crc_bits != 16)) return -1;
+  const bool sys = systematic != 0;
   switch (mode) {
-    case ORC_F32: return scl_decode_t<ArF32>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
-    case ORC_F64: return scl_decode_t<ArF64>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
-    case ORC_FIX: return scl_decode_t<ArFix>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st);
+    case ORC_F32: return scl_decode_t<ArF32>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st, sys);
+    case ORC_F64: return scl_decode_t<ArF64>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st, sys);
+    case ORC_FIX: return scl_decode_t<ArFix>(n, info_mask, crc_bits, L, llr, u_hat, status, pm_out, st, sys);
   }
   return -1;
 }
 
 int orc_scl_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
                          const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
-                         orc_stats* st) {
+                         orc_stats* st, int systematic) {
   const int n = log2_exact(N);
   if (n < 0) return -1;
   const size_t esz = mode == ORC_F32 ? 4 : (mode == ORC_F64 ? 8 : 1);
@@ -1188,8 +1251,14 @@ int orc_scl_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits
   for (int64_t b = 0; b < B; ++b) {
     int rc = orc_scl_decode(mode, N, info_mask, crc_bits, L,
                             (const uint8_t*)llr + (size_t)b * N * esz, u.data(), status + b,
-                            nullptr, st ? st + b : nullptr);
+                            nullptr, st ? st + b : nullptr, systematic);
     if (rc) return rc;
+    // the payload: the first K - crc information bits of u, or with systematic encoding of
+    // the codeword estimate u F^(x)n
+    if (systematic) {
+      std::vector<uint8_t> x(u);
+      orc_polar_transform(N, x.data(), u.data());
+    }
     int q = 0;
     for (int j = 0; j < N && q < k; ++j)
       if (info_mask[j]) payload[b * k + q++] = u[j];

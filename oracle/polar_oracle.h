@@ -63,6 +63,12 @@ int orc_encode_batch(int N, const uint8_t* info_mask, int crc_bits,
 /* SC decoding of one frame.  llr points to N values of the mode's input type
  * (float for F32, double for F64, int8_t for FIX).  Writes u_hat[N] and, if
  * leaf_llr is not NULL, the leaf LLR of every position as double. */
+/* Systematic encoding of B payloads (Section 2.2.2, last paragraph; Section 4): the codeword
+ * shows the message (payload, then CRC) at the information positions.  The decoders'
+ * `systematic` flag checks the CRC on, and reads the payload from, the codeword estimate. */
+int orc_encode_systematic_batch(int N, const uint8_t* info_mask, int crc_bits,
+                                const uint8_t* payload, int64_t B, uint8_t* codeword);
+
 int orc_sc_decode(int mode, int N, const uint8_t* info_mask, const void* llr,
                   uint8_t* u_hat, double* leaf_llr);
 
@@ -75,13 +81,13 @@ double orc_leaf_llr(int mode, int N, const void* llr, const uint8_t* prefix, int
  * path's metric as double).  */
 int orc_scs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st);
+                   orc_stats* st, int systematic);
 
 /* Batch helper: frames [B][N] -> payload[B][K-r], status[B], per-frame stats
  * (may be NULL; layout orc_stats[B]). */
 int orc_scs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
                          int L, const void* llr, int64_t B, uint8_t* payload,
-                         uint8_t* status, orc_stats* st);
+                         uint8_t* status, orc_stats* st, int systematic);
 
 /* Fast simplified decoding (Sections 2.2.2, 2.2.4, 3 and 4).  Node classes: */
 enum { ORC_NODE_R0 = 0, ORC_NODE_R1 = 1, ORC_NODE_REP = 2, ORC_NODE_SPC = 3 };
@@ -104,27 +110,29 @@ int orc_node_candidates(int mode, int type, int lam, const double* alpha, double
  * of paths taken (which may exceed cap), or -1 for bad arguments. */
 int orc_scs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                   const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap);
+                  orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap,
+                  int systematic);
 int orc_fsscs_trace(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                     int types, const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap);
+                    orc_stats* st, uint32_t* seq, int32_t* pl, double* pm, int cap,
+                    int systematic);
 
 /* FSSCS-RM decoding of one frame (stack rules as orc_scs_decode, one iteration per node). */
 int orc_fsscs_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int D, int L,
                      int types, const void* llr, uint8_t* u_hat, uint8_t* status,
-                     double* pm_out, orc_stats* st);
+                     double* pm_out, orc_stats* st, int systematic);
 int orc_fsscs_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int D,
                            int L, int types, const void* llr, int64_t B, uint8_t* payload,
-                           uint8_t* status, orc_stats* st);
+                           uint8_t* status, orc_stats* st, int systematic);
 
 /* CA-SCL decoding of one frame (Section 2.2.3): list size L, CRC selection among the final
  * paths (status OK, or FALLBACK when every path fails the CRC). */
 int orc_scl_decode(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
                    const void* llr, uint8_t* u_hat, uint8_t* status, double* pm_out,
-                   orc_stats* st);
+                   orc_stats* st, int systematic);
 int orc_scl_decode_batch(int mode, int N, const uint8_t* info_mask, int crc_bits, int L,
                          const void* llr, int64_t B, uint8_t* payload, uint8_t* status,
-                         orc_stats* st);
+                         orc_stats* st, int systematic);
 
 /* Brute-force ML over all 2^K information words (K <= 20): discrepancy
  * disc(c) = sum_{j: c_j != HD(llr_j)} |llr_j| in binary64.  Returns the minimum in

@@ -1,6 +1,7 @@
 """The hand-worked pins are sharp: each plausible slip in the oracle's stack rules, node
-sums or fixed-point metric, planted in a copy of the oracle source and built on the CPU,
-makes the golden tests of test_oracle_golden_search.py fail.  The copies are loaded in
+sums, fixed-point metric or systematic encoding, planted in a copy of the oracle source and
+built on the CPU, makes the golden tests (test_oracle_golden_search.py,
+test_oracle_systematic.py) fail.  The copies are loaded in
 child processes (POLAR_ORACLE_LIB), never in this one."""
 import os
 import subprocess
@@ -12,7 +13,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "polar_oracle.cpp")
-GOLDEN_TESTS = os.path.join(ROOT, "tests", "test_oracle_golden_search.py")
+GOLDEN_TESTS = [os.path.join(ROOT, "tests", f) for f in
+                ("test_oracle_golden_search.py", "test_oracle_systematic.py")]
 
 # name -> (text in the oracle source, replacement); the first occurrence is replaced
 MUTANTS = {
@@ -50,6 +52,13 @@ MUTANTS = {
     # reading R18: int16 metric saturation
     "metric_without_saturation": ("return s > 32767 ? 32767 : s;", "return s;"),
     "metric_wraps_int16": ("return s > 32767 ? 32767 : s;", "return (int)(int16_t)s;"),
+    # systematic encoding: CRC read from u, frozen positions kept, payload read from u
+    "systematic_crc_reads_u": ("if (!sys) return crc_passes(N, info, crc_bits, u);",
+                               "return crc_passes(N, info, crc_bits, u);"),
+    "systematic_encoder_keeps_frozen": (
+        "      if (!info_mask[j]) u[j] = 0;\n    orc_polar_transform(N, u.data(), codeword + b * N);",
+        "      if (false) u[j] = 0;\n    orc_polar_transform(N, u.data(), codeword + b * N);"),
+    "systematic_payload_from_u": ("    if (systematic) {", "    if (false) {"),
 }
 
 
@@ -69,8 +78,8 @@ def _build(name, tmp):
 
 def _run_golden(lib):
     env = dict(os.environ, POLAR_ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        GOLDEN_TESTS], cwd=ROOT, env=env, capture_output=True, text=True,
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"]
+                       + GOLDEN_TESTS, cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=300)
     return r.returncode, r.stdout[-2000:]
 
