@@ -73,6 +73,22 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_d
 int polar_construct_set(int32_t N, const uint8_t* info_mask, int32_t crc_bits,
                         polar_code** out);
 
+/* A systematic twin of `code` (Section 2.2.2, last paragraph; Section 4): the same N, K,
+ * information set and CRC, but the encoders put the message (payload, then CRC) into the
+ * codeword itself at the information positions (two passes of the transform: message at
+ * the information positions of v, u = v F^(x)n cleared at the frozen positions, c =
+ * u F^(x)n), and every decoder checks the CRC on, and reads the payload from, the
+ * estimated codeword at the information positions.  The decoders' search itself is
+ * unchanged.  On success *out receives a new code released with polar_code_free.
+ * Errors: POLAR_EINVAL for NULL arguments; POLAR_EUNSUPPORTED when the two-pass encoder
+ * does not show every message at this information set (checked on the unit messages; a
+ * set with a frozen index between two information indices in the bit-subset order may
+ * fail, constructed sets never do). */
+int polar_code_systematic(const polar_code* code, polar_code** out);
+
+/* 1 for a systematic code, 0 otherwise; POLAR_EINVAL for NULL. */
+int polar_code_is_systematic(const polar_code* code);
+
 /* Read back the parameters; any output pointer may be NULL.  info_mask_or_null, if
  * given, receives N bytes: 1 for an information position, 0 for a frozen one. */
 int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,
@@ -83,7 +99,8 @@ void polar_code_free(polar_code* code);
 /* -- encoding (Section 2.1: u at the information set, zeros elsewhere, c = u F^(x)n) -- */
 
 /* Host encoder.  payload: B x (K - crc_bits) bits, row-major; codeword: B x N bits,
- * row-major.  The CRC remainder of each payload is appended when crc_bits = 16. */
+ * row-major.  The CRC remainder of each payload is appended when crc_bits = 16.  A
+ * systematic code (polar_code_systematic) is encoded systematically. */
 int polar_encode(const polar_code* code, const uint8_t* payload, uint8_t* codeword,
                  int64_t B);
 

@@ -24,7 +24,8 @@ NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_CODES = 16 << 20, 64
 SCS_STATUS_OK, SCS_STATUS_FALLBACK, SCS_STATUS_EXHAUSTED = 1, 2, 4
 SCS_LLR_F32, SCS_LLR_I8 = 0, 1
 
-EXPORTS = ("polar_construct", "polar_construct_set", "polar_code_query", "polar_code_free", "polar_encode",
+EXPORTS = ("polar_construct", "polar_construct_set", "polar_code_systematic",
+           "polar_code_is_systematic", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch",
            "scs_decode_mixed_noalloc", "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
@@ -77,6 +78,8 @@ def lib():
             vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
             L.polar_construct.argtypes = [i32, i32, i32, dbl, ctypes.POINTER(vp)]
             L.polar_construct_set.argtypes = [i32, vp, i32, ctypes.POINTER(vp)]
+            L.polar_code_systematic.argtypes = [vp, ctypes.POINTER(vp)]
+            L.polar_code_is_systematic.argtypes = [vp]
             L.polar_code_query.argtypes = [vp, vp, vp, vp, vp]
             L.polar_code_free.argtypes = [vp]
             L.polar_code_free.restype = None
@@ -97,7 +100,8 @@ def lib():
             L.scl_decode_batch.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, vp]
             L.polar_strerror.argtypes = [ctypes.c_int]
             L.polar_strerror.restype = ctypes.c_char_p
-            for n in ("polar_construct", "polar_construct_set", "polar_code_query", "polar_encode", "polar_encode_device",
+            for n in ("polar_construct", "polar_construct_set", "polar_code_systematic",
+                      "polar_code_is_systematic", "polar_code_query", "polar_encode", "polar_encode_device",
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_decode_mixed_noalloc",
                       "scs_mixed_prepare", "scs_mixed_launch",
@@ -171,6 +175,19 @@ def polar_construct_set(info_mask: np.ndarray, crc_bits: int) -> int:
     _check(lib().polar_construct_set(int(m.size), m.ctypes.data, int(crc_bits), ctypes.byref(h)),
            "polar_construct_set")
     return h.value
+
+
+def polar_code_systematic(handle: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().polar_code_systematic(handle, ctypes.byref(h)), "polar_code_systematic")
+    return h.value
+
+
+def polar_code_is_systematic(handle: int) -> bool:
+    rc = lib().polar_code_is_systematic(handle)
+    if rc < 0:
+        _check(rc, "polar_code_is_systematic")
+    return rc == 1
 
 
 def polar_code_query(handle: int):
@@ -356,6 +373,16 @@ class PolarCode:
             self.handle = polar_construct_set(m, crc_bits)
         self.N, self.K, self.crc_bits, self.info_mask = polar_code_query(self.handle)
         self.design_db = design_db
+        self.systematic = False
+
+    def make_systematic(self) -> "PolarCode":
+        """The systematic twin of this code (polar_code_systematic): a new PolarCode."""
+        twin = PolarCode.__new__(PolarCode)
+        twin.handle = polar_code_systematic(self.handle)
+        twin.N, twin.K, twin.crc_bits, twin.info_mask = polar_code_query(twin.handle)
+        twin.design_db = self.design_db
+        twin.systematic = polar_code_is_systematic(twin.handle)
+        return twin
 
     @classmethod
     def from_set(cls, info_mask, crc_bits: int = 0) -> "PolarCode":

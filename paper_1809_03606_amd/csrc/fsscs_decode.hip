@@ -559,6 +559,8 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
     cand_slot = p;
   }
 
+  // systematic encoding: the payload is read from the codeword (the path's bits re-encoded)
+  if (code.systematic) out = polar_transform_row(out, lane, N, W);
   if (lane < W) {
     uint32_t iw = infow;
     int k = code.pre[lane];

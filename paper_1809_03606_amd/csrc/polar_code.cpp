@@ -220,6 +220,13 @@ void finish_code(polar_code* c) {
     std::vector<uint16_t> share(N, 0);
     for (int r = 0; r < K; ++r)
       share[c->info_pos[r]] = r < kp ? c->crc_unit[r] : (uint16_t)(1u << (crc_bits - 1 - (r - kp)));
+    // Systematic encoding: the message sits in the codeword x = u F^(x)n, where x_j is the
+    // xor of u_i over every i whose index contains the bits of j.  So decided bit u_i
+    // carries the shares of every information position j inside i (a subset sum).
+    if (c->systematic)
+      for (int b = 1; b < N; b <<= 1)
+        for (int i = 0; i < N; ++i)
+          if (i & b) share[i] ^= share[i ^ b];
     c->crc_syn.assign((size_t)nbytes * 256, 0);
     for (int b = 0; b < nbytes; ++b)
       for (int v = 1; v < 256; ++v) {
@@ -232,9 +239,79 @@ void finish_code(polar_code* c) {
   build_node_table(c);
 }
 
+// x = u F^(x)n on bits packed 64 to a word: position j takes j xor (j + d) for every
+// distance d with bit d of j clear (a masked shift within a word, then whole words).
+void transform_packed(uint64_t* x, int N) {
+  static const uint64_t kLow[6] = {0x5555555555555555ull, 0x3333333333333333ull,
+                                   0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
+                                   0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+  const int nw = (N + 63) / 64;
+  for (int s = 0; s < 6 && (1 << s) < N; ++s)
+    for (int w = 0; w < nw; ++w) x[w] ^= (x[w] >> (1 << s)) & kLow[s];
+  for (int dw = 1; dw < nw; dw <<= 1)
+    for (int w = 0; w < nw; ++w)
+      if ((w & dw) == 0) x[w] ^= x[w + dw];
+}
+
+// The information positions, packed 64 to a word.
+static void info_packed(const polar_code* c, uint64_t* m) {
+  for (int w = 0; w < (c->N + 63) / 64; ++w)
+    m[w] = (uint64_t)c->info_words[2 * w] | ((uint64_t)c->info_words[2 * w + 1] << 32);
+}
+
+// Systematic encoding of message v (at the information positions): u = v F^(x)n cleared
+// at the frozen positions, x = u F^(x)n.
+void encode_systematic_packed(const polar_code* c, uint64_t* x) {
+  uint64_t m[32];
+  info_packed(c, m);
+  transform_packed(x, c->N);
+  for (int w = 0; w < (c->N + 63) / 64; ++w) x[w] &= m[w];
+  transform_packed(x, c->N);
+}
+
+// True when the systematic encoder shows every message at the information positions: the
+// encoder is linear, so it suffices that each unit message comes back as itself.  Sets
+// closed upwards in the bit-subset order (every constructed set) always pass.
+bool systematic_shows_message(const polar_code* c) {
+  const int nw = (c->N + 63) / 64;
+  uint64_t m[32], x[32];
+  info_packed(c, m);
+  for (int p : c->info_pos) {
+    std::fill(x, x + nw, 0ull);
+    x[p >> 6] = 1ull << (p & 63);
+    encode_systematic_packed(c, x);
+    for (int w = 0; w < nw; ++w)
+      if ((x[w] & m[w]) != (w == (p >> 6) ? 1ull << (p & 63) : 0ull)) return false;
+  }
+  return true;
+}
+
 }  // namespace polarscs
 
 extern "C" {
+
+int polar_code_systematic(const polar_code* code, polar_code** out) {
+  if (!code || !out) return POLAR_EINVAL;
+  *out = nullptr;
+  if (!polarscs::systematic_shows_message(code)) return POLAR_EUNSUPPORTED;
+  polar_code* c = new (std::nothrow) polar_code;
+  if (!c) return POLAR_ENOMEM;
+  c->N = code->N;
+  c->K = code->K;
+  c->crc = code->crc;
+  c->logn = code->logn;
+  c->systematic = 1;
+  c->uid = polarscs::g_next_uid.fetch_add(1);
+  c->info = code->info;
+  polarscs::finish_code(c);
+  *out = c;
+  return POLAR_OK;
+}
+
+int polar_code_is_systematic(const polar_code* code) {
+  if (!code) return POLAR_EINVAL;
+  return code->systematic ? 1 : 0;
+}
 
 int polar_code_query(const polar_code* code, int32_t* N, int32_t* K, int32_t* crc_bits,
                      uint8_t* info_mask_or_null) {
@@ -267,16 +344,10 @@ int polar_encode(const polar_code* code, const uint8_t* payload, uint8_t* codewo
     std::fill(x.begin(), x.end(), 0);
     for (int j = 0; j < code->K; ++j)
       if (msg[j]) x[code->info_pos[j] >> 6] |= 1ull << (code->info_pos[j] & 63);
-    // u F^(x)n as butterflies on packed bits: position j takes j xor (j + d) for every
-    // distance d with bit d of j clear.  Within a 64-bit word that is a masked shift.
-    static const uint64_t kLow[6] = {0x5555555555555555ull, 0x3333333333333333ull,
-                                     0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
-                                     0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
-    for (int s = 0; s < 6 && (1 << s) < N; ++s)
-      for (int w = 0; w < nw; ++w) x[w] ^= (x[w] >> (1 << s)) & kLow[s];
-    for (int dw = 1; dw < nw; dw <<= 1)
-      for (int w = 0; w < nw; ++w)
-        if ((w & dw) == 0) x[w] ^= x[w + dw];
+    if (code->systematic)
+      polarscs::encode_systematic_packed(code, x.data());
+    else
+      polarscs::transform_packed(x.data(), N);  // u F^(x)n
     uint8_t* cw = codeword + f * N;
     for (int j = 0; j < N; ++j) cw[j] = (uint8_t)((x[j >> 6] >> (j & 63)) & 1);
   }

@@ -10,6 +10,7 @@ struct polar_code {
   int32_t K = 0;      // information positions, CRC bits included
   int32_t crc = 0;    // 0 or 16
   int32_t logn = 0;
+  int32_t systematic = 0;  // 1: the message sits in the codeword at the information set
   uint64_t uid = 0;   // process-unique id (device table caches key on it)
   std::vector<uint8_t> info;     // N bytes, 1 = information position
   std::vector<int32_t> info_pos; // K positions, ascending
@@ -32,4 +33,7 @@ namespace polarscs {
 uint16_t crc16_payload(const uint8_t* bits, int nbits);
 void build_node_table(polar_code* c);
 void finish_code(polar_code* c);
+void transform_packed(uint64_t* x, int N);
+void encode_systematic_packed(const polar_code* c, uint64_t* x);
+bool systematic_shows_message(const polar_code* c);
 }

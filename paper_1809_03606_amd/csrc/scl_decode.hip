@@ -432,7 +432,9 @@ __device__ __forceinline__ void scl_frames(const CodeArgs& code, const FrameJob&
       }
     }
     const uint32_t oslot = readlane(phys, out);
-    const uint32_t orow = lane < W ? U[oslot * WP + lane] : 0u;
+    uint32_t orow = lane < W ? U[oslot * WP + lane] : 0u;
+    // systematic encoding: the payload is read from the re-encoded path
+    if (code.systematic) orow = polar_transform_row(orow, lane, N, W);
     if (lane < W) {
       uint32_t iw = infow;
       int k = code.pre[lane];

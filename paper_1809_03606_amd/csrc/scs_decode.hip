@@ -252,7 +252,9 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
     cand_slot = p;
   }
 
-  // output: payload = the first K - r information bits of the output path
+  // output: payload = the first K - r information bits of the output path (systematic
+  // encoding: of its codeword, the path's bits re-encoded)
+  if (code.systematic) out = polar_transform_row(out, lane, N, W);
   if (lane < W) {
     uint32_t iw = infow;
     int k = code.pre[lane];
@@ -401,12 +403,12 @@ __global__ __launch_bounds__(256) void encode_kernel(CodeArgs code, const uint16
       ++k;
     }
   }
-  // u F^(x)n: in-word butterflies, then across words
-  constexpr uint32_t kLow[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu, 0x0000FFFFu};
-  for (int s = 0; s < 5 && (1 << s) < code.N; ++s) x ^= (x >> (1 << s)) & kLow[s];
-  for (int dw = 1; dw < code.W; dw <<= 1) {
-    const uint32_t y = xor_lane_rt(x, dw);
-    if (!(lane & dw)) x ^= y;
+  // u F^(x)n.  Systematic encoding: the message placed this way is v; its transform,
+  // cleared at the frozen positions, is the u that is sent through the transform.
+  x = polar_transform_row(x, lane, code.N, code.W);
+  if (code.systematic) {
+    x &= lane < code.W ? code.info[lane] : 0u;
+    x = polar_transform_row(x, lane, code.N, code.W);
   }
   if (lane < code.W) {
     uint8_t* dst = codeword + f * code.N + lane * 32;

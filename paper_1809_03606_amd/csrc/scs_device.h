@@ -13,6 +13,7 @@ namespace polarscs {
 // Kernel-argument copy of a code's tables.
 struct CodeArgs {
   int32_t N, K, crc, logn, W, kp;
+  int32_t systematic;  // read the payload from the re-encoded path (systematic encoding)
   uint32_t info[64];
   uint16_t pre[64];
   const uint16_t* crc_tab;  // device copy of polar_code::crc_syn (null without a CRC)
@@ -29,6 +30,7 @@ inline CodeArgs make_args(const polar_code* c) {
   a.logn = c->logn;
   a.W = c->words();
   a.kp = c->payload_bits();
+  a.systematic = c->systematic;
   std::memcpy(a.info, c->info_words, sizeof a.info);
   std::memcpy(a.pre, c->info_prefix, sizeof a.pre);
   return a;
@@ -99,6 +101,19 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 }
 
 __device__ __forceinline__ int msb(uint32_t x) { return 31 - __builtin_clz(x); }
+
+// x = u F^(x)n of a bit vector held one 32-bit word per lane (lane w: bits 32w..32w+31,
+// lanes >= W hold 0; Section 2.1): butterflies within each word, then between lanes.  Every
+// lane of the wave takes part.
+__device__ __forceinline__ uint32_t polar_transform_row(uint32_t x, int lane, int N, int W) {
+  constexpr uint32_t kLow[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu, 0x0000FFFFu};
+  for (int s = 0; s < 5 && (1 << s) < N; ++s) x ^= (x >> (1 << s)) & kLow[s];
+  for (int dw = 1; dw < W; dw <<= 1) {
+    const uint32_t y = xor_lane_rt(x, dw);
+    if (!(lane & dw)) x ^= y;
+  }
+  return x;
+}
 
 // Bits [0, lim) of a lane-per-word bit vector.
 __device__ __forceinline__ uint32_t prefix_mask(int lane, int lim) {

@@ -189,3 +189,39 @@ def test_construct_from_an_explicit_set(lib):
         assert lib.polar_construct_set(N, m.ctypes.data, crc, ctypes.byref(h)) == binding.POLAR_EINVAL
     assert lib.polar_construct_set(8, None, 0, ctypes.byref(h)) == binding.POLAR_EINVAL
     assert lib.polar_construct_set(8, ok.ctypes.data, 0, None) == binding.POLAR_EINVAL
+
+
+@pytest.mark.parametrize("N,K,crc", [(2, 1, 0), (8, 4, 0), (64, 32, 16), (256, 77, 16),
+                                     (1024, 512, 16), (2048, 1707, 16)])
+def test_systematic_twin_encodes_like_the_oracle(lib, N, K, crc):
+    code = binding.PolarCode(N, K, crc, 2.0)
+    twin = code.make_systematic()
+    assert twin.systematic and not code.systematic
+    assert (twin.N, twin.K, twin.crc_bits) == (N, K, crc) and (twin.info_mask == code.info_mask).all()
+    pay = channel.payload_bits(31, N, 0, 32, K - crc)
+    assert (twin.encode(pay) == oracle.encode_batch(code.info_mask, crc, pay, systematic=True)).all()
+    assert (code.encode(pay) == oracle.encode_batch(code.info_mask, crc, pay)).all()
+
+
+def test_systematic_twin_needs_a_set_that_shows_the_message(lib):
+    """PC(4,3) with set {0, 1, 3}: the unit message at 3 encodes (by hand: v = e3,
+    u = v F = 1111, cleared at 2: 1101, x = 1011) to a codeword reading (1, 0, 1) at the
+    set, not (0, 0, 1): refused.  The set {1, 7} of N = 8 is not contiguous in the subset
+    order but does show every message, and is accepted; both agree with the oracle."""
+    bad = np.array([1, 1, 0, 1], np.uint8)
+    assert (oracle.encode_batch(bad, 0, np.array([[0, 0, 1]], np.uint8), systematic=True)
+            == np.array([[1, 0, 1, 1]], np.uint8)).all()
+    with pytest.raises(binding.PolarError) as e:
+        binding.PolarCode.from_set(bad, 0).make_systematic()
+    assert e.value.code == binding.POLAR_EUNSUPPORTED
+    good = np.zeros(8, np.uint8)
+    good[[1, 7]] = 1
+    msgs = np.array([[1, 0], [0, 1], [1, 1]], np.uint8)
+    twin = binding.PolarCode.from_set(good, 0).make_systematic()
+    assert (twin.encode(msgs) == oracle.encode_batch(good, 0, msgs, systematic=True)).all()
+    assert (twin.encode(msgs)[:, [1, 7]] == msgs).all()
+    # random upward-closed sets (constructed) are accepted
+    for N, K in [(32, 5), (512, 300)]:
+        binding.PolarCode(N, K, 0, 1.0).make_systematic()
+    assert lib.polar_code_is_systematic(None) == binding.POLAR_EINVAL
+    assert lib.polar_code_systematic(None, None) == binding.POLAR_EINVAL
