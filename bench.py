@@ -88,7 +88,12 @@ def parse():
                     help="closed-loop requests timed for the latency percentiles of the sweep")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="offered load as a fraction of the measured saturated capacity")
+                    help="offered load as a fraction of the mixed batch's sustained frame rate "
+                         "(measured in the same run)")
+    ap.add_argument("--serve-rate-frames", type=int, default=500_000,
+                    help="frames of the i.i.d. mixed batch that measures that rate")
+    ap.add_argument("--serve-pool", type=int, default=4096,
+                    help="distinct requests generated for the serving run (replayed)")
     ap.add_argument("--mixed-frames", type=int, default=2_000_000)
     ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the HBM traffic record from four rocprofv3 --pmc output folders "
@@ -597,19 +602,12 @@ def main():
     print(json.dumps(line))
 
 
-def run_mixed(args):
-    """Mixed batch: frames drawn uniformly over N in {128..2048}, rate in {1/4..5/6} (25
-    codes, CRC-16), D in {8, 32, 64}, L = 8, Eb/N0 ~ U[1.5, 3.5] dB, decoded (a) in one
-    persistent launch replayed from a captured graph and (b) as one launch per (code, D)."""
-    import torch
-
+def mixed_batch(torch, dev, B, seed, pcs, codes, stream, Lp=8, crc=16):
+    """Frames of the mixed workload generated on the device, laid out grouped by (code, D):
+    returns (frames descriptors, LLRs, reference payloads, groups, grouped order, payload
+    bits per frame)."""
     from paper_1809_03606_amd import binding, channel
 
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    B, Lp, crc, seed = args.mixed_frames, 8, 16, 4
-    codes = channel.mixed_codes()
-    pcs = [binding.PolarCode(n, k, crc, 2.0) for (n, k) in codes]
     cidx, Dv, eb = channel.mixed_draw(seed, B)
     dsel = {8: 0, 32: 1, 64: 2}
     gkey = cidx.astype(np.int64) * 3 + np.vectorize(dsel.get)(Dv)
@@ -621,7 +619,6 @@ def run_mixed(args):
     llr_off[grouped] = np.concatenate([[0], np.cumsum(Nf[grouped])[:-1]])
     out_off[grouped] = np.concatenate([[0], np.cumsum(kpf[grouped])[:-1]])
     tot_llr, tot_out = int(Nf.sum()), int(kpf.sum())
-    stream = torch.cuda.Stream(device=dev)
     llr = torch.empty(tot_llr, dtype=torch.float32, device=dev)
     pay_ref = torch.empty(tot_out, dtype=torch.uint8, device=dev)
     groups = []  # (code, D, first grouped position, count)
@@ -645,10 +642,29 @@ def run_mixed(args):
             groups.append((c, d, lo, lo_o, cnt))
     stream.synchronize()
     log("mixed inputs ready: %d frames in %d (code, D) groups, %.1f s" % (B, len(groups), time.time() - t0))
-
     frames = np.zeros(B, binding.FRAME_DTYPE)
     frames["code"], frames["D"], frames["L"] = cidx, Dv, Lp
     frames["llr_off"], frames["out_off"] = llr_off, out_off
+    return frames, llr, pay_ref, groups, grouped, kpf
+
+
+def run_mixed(args):
+    """Mixed batch: frames drawn uniformly over N in {128..2048}, rate in {1/4..5/6} (25
+    codes, CRC-16), D in {8, 32, 64}, L = 8, Eb/N0 ~ U[1.5, 3.5] dB, decoded (a) in one
+    persistent launch replayed from a captured graph and (b) as one launch per (code, D)."""
+    import torch
+
+    from paper_1809_03606_amd import binding, channel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    B, Lp, crc, seed = args.mixed_frames, 8, 16, 4
+    codes = channel.mixed_codes()
+    pcs = [binding.PolarCode(n, k, crc, 2.0) for (n, k) in codes]
+    stream = torch.cuda.Stream(device=dev)
+    frames, llr, pay_ref, groups, grouped, kpf = mixed_batch(torch, dev, B, seed, pcs, codes,
+                                                             stream, Lp, crc)
+    tot_out = int(kpf.sum())
     ctx = binding.ScsContext(0)
     ctx_plain = binding.ScsContext(0)  # one launch per configuration, library launch shapes
     pay_m = torch.empty(tot_out, dtype=torch.uint8, device=dev)
@@ -922,9 +938,10 @@ def run_depth(args):
     print(json.dumps(line))
 
 
-def serve_pool(seed, n_req, codes, pcs):
-    """A pool of requests of the mixed distribution (code, D), 1..256 frames each, LLRs
-    generated on the device with the library's encoder and copied to host memory."""
+def serve_pool(seed, n_req, codes, pcs, on_device=True):
+    """A pool of requests of the mixed distribution (code, D, Eb/N0 per request), 1..256
+    frames each, LLRs generated on the device with the library's encoder; they stay there
+    (device-resident requests) or are copied to host memory."""
     import torch
 
     from paper_1809_03606_amd import channel
@@ -942,64 +959,100 @@ def serve_pool(seed, n_req, codes, pcs):
         cw = torch.empty((m, n), dtype=torch.uint8, device="cuda")
         pcs[c].encode_device(pay, cw)
         ebs = torch.full((m,), float(rng.uniform(1.5, 3.5)), dtype=torch.float64, device="cuda")
-        llr = channel.device_llr_per_frame(torch, gen, cw, ebs, k / n).cpu().numpy()
-        pool.append(Request(rid=rid, code=c, D=int(rng.choice([8, 32, 64])), L=8, llr=llr))
+        llr = channel.device_llr_per_frame(torch, gen, cw, ebs, k / n)
+        pool.append(Request(rid=rid, code=c, D=int(rng.choice([8, 32, 64])), L=8,
+                            llr=llr if on_device else llr.cpu().numpy()))
+    torch.cuda.synchronize()
     return pool
 
 
 def run_serve(args):
     """Poisson arrivals of requests (1..256 frames of one code / D from the mixed
-    distribution) at args.serve_load x the saturated capacity, admitted by device-memory
-    budget into 4 concurrent slots; reports latency percentiles and sustained payload bit/s."""
+    distribution, LLRs resident on the device) at args.serve_load x the sustained frame
+    rate of the mixed batch's persistent launch (measured here on an i.i.d. batch of the same
+    distribution), admitted by device-memory budget into 4 concurrent slots; reports request
+    latency percentiles and sustained payload bit/s."""
     import copy
 
     import torch
 
-    from paper_1809_03606_amd import binding, channel
+    from paper_1809_03606_amd import binding, channel, tune
     from paper_1809_03606_amd.serve import GpuBackend, Server
 
-    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
     codes = channel.mixed_codes()
     pcs = [binding.PolarCode(n, k, 16, 2.0) for (n, k) in codes]
     shapes = [(n, k - 16) for (n, k) in codes]
-    pool = serve_pool(5, 512, codes, pcs)
-    log("serve: pool of %d requests ready" % len(pool))
-    be = GpuBackend(pcs, n_slots=4, max_frames=8192)
-    # saturated capacity: the whole pool submitted at once
-    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=8192)
+    # the mixed batch's sustained rate: one persistent launch over an i.i.d. batch
+    stream = torch.cuda.Stream(device=dev)
+    Bm = args.serve_rate_frames
+    frames, llr, _, _, _, kpf = mixed_batch(torch, dev, Bm, 44, pcs, codes, stream)
+    ctx = binding.ScsContext(0)
+    if tune.apply_mixed(ctx, pcs, frames) is None:
+        ctx.configure(4)
+    pay = torch.empty(int(kpf.sum()), dtype=torch.uint8, device=dev)
+    st = torch.empty(Bm, dtype=torch.uint8, device=dev)
+    binding.scs_mixed_prepare(ctx.handle, [p.handle for p in pcs], frames, stream)
+    ms = []
+    for r in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        binding.scs_mixed_launch(ctx.handle, binding.SCS_LLR_F32, llr, pay, st, None, stream)
+        b.record(stream)
+        stream.synchronize()
+        if r:
+            ms.append(a.elapsed_time(b))
+    c4_fps = Bm / (np.mean(ms) * 1e-3)
+    del llr, pay, st
+    ctx.close()
+    log("serve: mixed-batch sustained rate %.0f frames/s (%d frames, %.1f ms per launch)"
+        % (c4_fps, Bm, np.mean(ms)))
+    pool = serve_pool(5, args.serve_pool, codes, pcs, on_device=True)
+    pool_frames = sum(r.frames for r in pool)
+    log("serve: pool of %d device-resident requests (%d frames) ready" % (len(pool), pool_frames))
+    be = GpuBackend(pcs, n_slots=4, max_frames=16384, host_inputs=False)
+    # saturated capacity of the server: the whole pool submitted at once, twice
+    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=16384)
     t0 = time.perf_counter()
-    for r in pool:
-        srv.submit(copy.copy(r))
+    for rep_ in range(2):
+        for r in pool:
+            srv.submit(copy.copy(r))
     srv.drain()
-    cap_s = time.perf_counter() - t0
-    frames = sum(r.frames for r in pool)
-    cap_fps = frames / cap_s
-    log("serve: saturated capacity %.0f frames/s (%.1f s)" % (cap_fps, cap_s))
+    cap_fps = 2 * pool_frames / (time.perf_counter() - t0)
+    log("serve: saturated server capacity %.0f frames/s" % cap_fps)
     # Poisson arrivals at the offered load for the run time
     rng = np.random.default_rng(6)
-    rate = args.serve_load * cap_fps / (frames / len(pool))  # requests per second
+    mean_frames = pool_frames / len(pool)
+    offered_fps = args.serve_load * c4_fps
+    rate = offered_fps / mean_frames  # requests per second
     arrivals, t, k = [], 0.0, 0
     while t < args.serve_seconds:
         t += float(rng.exponential(1.0 / rate))
-        r = copy.copy(pool[k % len(pool)])
+        r = copy.copy(pool[int(rng.integers(len(pool)))])
         r.rid = k
         arrivals.append((t, r))
         k += 1
-    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=8192)
-    log("serve: replaying %d requests over %.0f s" % (len(arrivals), args.serve_seconds))
-    rep = srv.run(arrivals)
+    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=16384)
+    log("serve: replaying %d requests over %.0f s (%.0f frames/s offered)"
+        % (len(arrivals), args.serve_seconds, offered_fps))
+    rep = srv.run(arrivals, progress=lambda msg: log("serve: " + msg))
     line = {
         "metric": "p50/p99 request latency and sustained info Mbit/s, continuous-batching server",
         "value": rep["payload_mbps"], "unit": "Mbit/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": rep["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic: seeded BPSK/AWGN requests of the mixed distribution",
+        "data": "synthetic: seeded BPSK/AWGN requests of the mixed distribution, LLRs on the device",
         "config": {"workload": "serving: Poisson requests of 1-256 frames, mixed codes/D, "
-                               "4 slots, 1 GiB budget",
-                   "offered_load": args.serve_load, "capacity_frames_per_s": cap_fps,
+                               "4 slots, 1 GiB budget, device-resident LLRs",
+                   "offered_load": args.serve_load,
+                   "mixed_batch_frames_per_s": c4_fps,
+                   "offered_frames_per_s": offered_fps,
+                   "server_capacity_frames_per_s": cap_fps,
                    "requests": len(arrivals), "seconds": args.serve_seconds},
         "latency_ms": {"p50": rep["latency_ms_p50"], "p99": rep["latency_ms_p99"],
                        "mean": rep["latency_ms_mean"]},
+        "sustained_frames_per_s": rep["frames"] / rep["span_s"],
         "batches": rep["batches"], "max_concurrent_batches": be.max_concurrent,
     }
     print(json.dumps(line))

@@ -3,10 +3,12 @@
 Requests (one code, one D and L, 1..256 frames each) arrive over time.  The server keeps a
 FIFO of waiting requests and several device slots (one HIP stream and one decoder context
 each).  Whenever a slot is free it admits waiting requests, oldest first, while their
-device footprint fits the free part of the memory budget, packs their LLRs into the slot's
-pinned staging buffer, copies them to the device and enqueues one mixed-batch decode
-(``scs_decode_mixed``) plus the copy of the results back; batches of different slots run
-concurrently on the GPU.  A request that arrives while others are decoding joins the next
+device footprint fits the free part of the memory budget, and enqueues one mixed-batch
+decode (``scs_decode_mixed``) of all their frames plus the copy of the results back; batches
+of different slots run concurrently on the GPU.  A request's LLRs are either in host memory
+(packed into the slot's pinned staging buffer and copied to the device with the batch) or
+already on the device (a CUDA tensor, for example written there by a demodulator): then the
+batch's descriptors point at them where they are and nothing is copied in.  A request that arrives while others are decoding joins the next
 free slot: slots and budget are released as batches finish.
 
 Footprint of a request (bytes of device memory its frames hold while in flight): LLRs
@@ -44,7 +46,7 @@ class Request:
     code: int            # index into the server's code list
     D: int
     L: int
-    llr: np.ndarray      # float32 [frames][N]
+    llr: object          # float32 [frames][N]: numpy array, or CUDA tensor on the device
     t_arrival: float = 0.0
     t_admit: float = 0.0
     t_done: float = 0.0
@@ -62,25 +64,32 @@ class AdmissionError(ValueError):
 
 
 class GpuBackend:
-    """Device slots: a stream, a decoder context and pinned staging buffers each."""
+    """Device slots: a stream, a decoder context, output buffers and (host_inputs) pinned
+    staging buffers for requests whose LLRs are in host memory.  Requests with device LLRs
+    must have them written (and the writing stream synchronised) before submission."""
 
-    def __init__(self, codes, n_slots: int = 4, max_frames: int = 4096, device: int = 0):
+    def __init__(self, codes, n_slots: int = 4, max_frames: int = 4096, device: int = 0,
+                 host_inputs: bool = True):
         import torch
 
         self.torch = torch
         self.codes = codes  # list of binding.PolarCode
+        self.Ns = np.array([c.N for c in codes], np.int64)
+        self.kps = np.array([c.payload_bits for c in codes], np.int64)
+        self.handles = [c.handle for c in codes]
         self.dev = torch.device("cuda", device)
         maxN = max(c.N for c in codes)
         maxkp = max(c.payload_bits for c in codes)
         self.max_frames = max_frames
         self.max_concurrent = 0  # most batches seen in flight at once
         self.slots = []
+        stage = max_frames * maxN if host_inputs else 0
         for _ in range(n_slots):
             s = {
                 "stream": torch.cuda.Stream(device=self.dev),
                 "ctx": binding.ScsContext(device),
-                "h_llr": torch.empty(max_frames * maxN, dtype=torch.float32, pin_memory=True),
-                "d_llr": torch.empty(max_frames * maxN, dtype=torch.float32, device=self.dev),
+                "h_llr": torch.empty(stage, dtype=torch.float32, pin_memory=True),
+                "d_llr": torch.empty(stage, dtype=torch.float32, device=self.dev),
                 "d_pay": torch.empty(max_frames * maxkp, dtype=torch.uint8, device=self.dev),
                 "d_st": torch.empty(max_frames, dtype=torch.uint8, device=self.dev),
                 "h_pay": torch.empty(max_frames * maxkp, dtype=torch.uint8, pin_memory=True),
@@ -101,31 +110,50 @@ class GpuBackend:
     def submit(self, slot: int, reqs):
         torch = self.torch
         s = self.slots[slot]
-        n = sum(r.frames for r in reqs)
+        nr = len(reqs)
+        m = np.fromiter((r.frames for r in reqs), np.int64, nr)
+        n = int(m.sum())
         if n > self.max_frames:
             raise AdmissionError("batch of %d frames exceeds the slot size %d" % (n, self.max_frames))
+        code = np.fromiter((r.code for r in reqs), np.int64, nr)
+        Nr, kpr = self.Ns[code], self.kps[code]
+        first = np.cumsum(m) - m                          # first frame of each request
+        j = np.arange(n, dtype=np.int64) - np.repeat(first, m)  # frame within its request
         frames = np.zeros(n, binding.FRAME_DTYPE)
-        hl = s["h_llr"].numpy()
-        f = lo = lo_o = 0
-        spans = []
-        for r in reqs:
-            code = self.codes[r.code]
-            m = r.frames
-            hl[lo:lo + m * code.N] = r.llr.reshape(-1)
-            frames[f:f + m]["code"] = r.code
-            frames[f:f + m]["D"] = r.D
-            frames[f:f + m]["L"] = r.L
-            frames[f:f + m]["llr_off"] = lo + np.arange(m) * code.N
-            frames[f:f + m]["out_off"] = lo_o + np.arange(m) * code.payload_bits
-            spans.append((f, lo_o, m, code.payload_bits))
-            f += m
-            lo += m * code.N
-            lo_o += m * code.payload_bits
+        frames["code"] = np.repeat(code, m)
+        frames["D"] = np.repeat(np.fromiter((r.D for r in reqs), np.int64, nr), m)
+        frames["L"] = np.repeat(np.fromiter((r.L for r in reqs), np.int64, nr), m)
+        out0 = np.cumsum(m * kpr) - m * kpr
+        frames["out_off"] = np.repeat(out0, m) + j * np.repeat(kpr, m)
+        lo_o = int((m * kpr).sum())
+        on_device = [getattr(r.llr, "is_cuda", False) for r in reqs]
         st = s["stream"]
+        if all(on_device):
+            # descriptors point at the requests' own device LLRs, relative to the lowest
+            ptrs = np.fromiter((r.llr.data_ptr() for r in reqs), np.int64, nr)
+            base = int(ptrs.min())
+            if ((ptrs - base) % 4).any():
+                raise AdmissionError("device LLRs must be 4-byte aligned float32")
+            frames["llr_off"] = np.repeat((ptrs - base) // 4, m) + j * np.repeat(Nr, m)
+            llr_arg = base
+        elif not any(on_device):
+            if s["h_llr"].numel() == 0:
+                raise AdmissionError("this backend takes device LLRs only (host_inputs=False)")
+            hl = s["h_llr"].numpy()
+            l0 = np.cumsum(m * Nr) - m * Nr
+            for r, a in zip(reqs, l0):
+                hl[a:a + r.llr.size] = r.llr.reshape(-1)
+            lo = int((m * Nr).sum())
+            frames["llr_off"] = np.repeat(l0, m) + j * np.repeat(Nr, m)
+            with torch.cuda.stream(st):
+                s["d_llr"][:lo].copy_(s["h_llr"][:lo], non_blocking=True)
+            llr_arg = s["d_llr"]
+        else:
+            raise AdmissionError("a batch holds requests with host and with device LLRs")
+        spans = list(zip(first.tolist(), out0.tolist(), m.tolist(), kpr.tolist()))
         with torch.cuda.stream(st):
-            s["d_llr"][:lo].copy_(s["h_llr"][:lo], non_blocking=True)
-            binding.scs_decode_mixed(s["ctx"].handle, [c.handle for c in self.codes], frames,
-                                     binding.SCS_LLR_F32, s["d_llr"], s["d_pay"], s["d_st"], None, st)
+            binding.scs_decode_mixed(s["ctx"].handle, self.handles, frames, binding.SCS_LLR_F32,
+                                     llr_arg, s["d_pay"], s["d_st"], None, st)
             s["h_pay"][:lo_o].copy_(s["d_pay"][:lo_o], non_blocking=True)
             s["h_st"][:n].copy_(s["d_st"][:n], non_blocking=True)
             ev = torch.cuda.Event()
@@ -230,16 +258,22 @@ class Server:
             if self.step() == 0:
                 time.sleep(0.0002)
 
-    def run(self, arrivals, poll_s: float = 0.0002):
+    def run(self, arrivals, poll_s: float = 0.0002, progress=None, every_s: float = 10.0):
         """arrivals: list of (offset_seconds, Request), ascending offsets.  Replays them in
-        real time against the backend and drains the server."""
+        real time against the backend and drains the server; `progress(text)` is called
+        about every `every_s` seconds."""
         t0 = self.clock()
         k = 0
+        next_report = every_s
         while k < len(arrivals) or self.busy():
             now = self.clock() - t0
             while k < len(arrivals) and arrivals[k][0] <= now:
                 self.submit(arrivals[k][1], now=t0 + arrivals[k][0])
                 k += 1
+            if progress is not None and now >= next_report:
+                progress("%.0f s: %d arrived, %d completed, %d waiting, %d batches"
+                         % (now, k, len(self.completed), len(self.waiting), self.batches))
+                next_report += every_s
             if self.step() == 0:
                 time.sleep(poll_s)
         return self.report()
