@@ -114,7 +114,8 @@ def parse():
 
 
 KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
-                  "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h")
+                  "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h",
+                  "paper_1809_03606_amd/build.py")  # the compiler flags shape the kernel too
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
 COUNTERS_RECORD = os.path.join(ROOT, "profiles", "decoder_counters_n1024.json")
 CU_CYCLES_PER_S = 256 * 2.4e9  # MI355X: 256 CUs at 2.4 GHz

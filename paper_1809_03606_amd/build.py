@@ -23,9 +23,13 @@ SOURCES = ["polar_code.cpp", "scs_decode.hip", "fsscs_decode.hip", "scl_decode.h
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall",
           "-fno-fast-math", "-ffp-contract=off"]
-# Device code: gfx950 only; no packed-fp32 instructions (see the design notes).
+# Device code: gfx950 only; no packed-fp32 instructions (see the design notes).  The
+# decoders' control flow is wave-uniform (one frame per wavefront, every branch on scalar
+# values), so LLVM's CFG structurizer is told to leave uniform regions alone: it would
+# otherwise rewrite them into predicated form with extra scalar flag bookkeeping on every
+# branch, and the decoders are bound by scalar instruction issue.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-mllvm", "-structurizecfg-skip-uniform-regions=1"]
 
 
 def _compile(src: str) -> str:
