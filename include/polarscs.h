@@ -42,8 +42,9 @@ enum {
   SCS_STATUS_OK = 1,        /* output path passed the CRC (or there is no CRC) */
   SCS_STATUS_FALLBACK = 2,  /* every complete path failed the CRC; the first one is output */
   SCS_STATUS_EXHAUSTED = 4  /* decoding stopped because the stack emptied */
-  /* a status byte of 0: the safeguard bound of L N + L extensions was reached (the L
-   * counters keep every search below it, so it is not expected); payload unspecified */
+  /* a status byte of 0: the safeguard bound was reached (L N + L + 1 searches of the stack,
+   * each followed by at most N + 1 extensions; the L counters keep every search far below
+   * it, so it is not expected); payload unspecified */
 };
 
 /* LLR element types. */
@@ -158,8 +159,8 @@ typedef struct {
  *   D in [1, 256] (up to 64 slots per 64-lane bank of the stack), L in [1, 255].
  * Enqueued on hip_stream of the context's device; returns before the work runs.  The
  * result of a frame depends only on that frame's LLRs and (code, D, L).  Non-finite
- * LLRs give an unspecified output but the kernel still terminates: every frame stops
- * after at most L * N + L iterations. */
+ * LLRs give an unspecified output but the kernel still terminates (a frame makes at most
+ * L N extensions and L completions; a safeguard bound stops it in any case). */
 int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
                      int32_t llr_dtype, const void* llr_dev, int64_t n_frames,
                      uint8_t* payload_dev, uint8_t* status_dev, scs_stats* stats_dev,

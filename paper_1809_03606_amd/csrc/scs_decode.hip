@@ -81,10 +81,11 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   S.init(D, make_key(0u, key_lo(N, 0, 0u)));
   uint32_t next_seq = 1;
 
-  // fast path: the first child of the last extension ("candidate", kNone if none) wins
-  // whenever its key is below lb, a lower bound on every other live key
-  uint64_t cand = kNone, lb = 0ull;
-  int cand_slot = 0;
+  // The path extended next: slot p with key pk.  After an extension these are its first
+  // child (which took over the slot), and that child is extended without a search whenever
+  // its key is below lb, a lower bound on every other live key; kNone forces a search.
+  int p = 0;
+  uint64_t pk = kNone, lb = 0ull;
   // exact worst live key, kNone when unknown
   uint64_t maxk = kNone;
   int max_slot = 0;
@@ -99,39 +100,35 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   uint32_t st = 0u;
   uint32_t n_it = 0, n_sw = 0, n_cp = 0, n_sc = 0, n_fg = 0, n_ev = 0, n_dr = 0, n_pr = 0;
 
-  // at most L N extensions and L completions: an unreachable bound that still guarantees
-  // every wavefront leaves the loop
+  // The L counters bound the search to L N extensions and L completions; as a safeguard
+  // every stack search (at most N + 1 extensions follow one) spends one unit of a budget of
+  // L N + L + 1, so every wavefront leaves the loop whatever its inputs.
   uint32_t budget = (uint32_t)L * (uint32_t)N + (uint32_t)L + 1u;
   for (;;) {
-    if (budget == 0u) {
-      st = 0u;
-      break;
-    }
-    --budget;
     // ---- the best path -------------------------------------------------------------
-    int p;
-    uint64_t pk;
-    bool cont;
-    if (cand < lb) {
-      p = cand_slot;
-      pk = cand;
-      cont = true;
-    } else {
+    bool cont = true;  // the first child of the last extension, with no search
+    if (!(pk < lb)) {
+      if (budget == 0u) {
+        st = 0u;
+        break;
+      }
+      --budget;
       if (S.empty()) {
         st = SCS_STATUS_FALLBACK | SCS_STATUS_EXHAUSTED;
         out = fb;
         break;
       }
+      const uint64_t cand = pk;
       S.best(lane, p, pk, lb);
       cont = pk == cand;
     }
     // the slot stays live while the path is extended: its first child takes it over
     if (max_slot == p) maxk = kNone;
-    cand = kNone;
     const int i = N - (int)((uint32_t)pk >> kSeqBits);  // length of the best path
 
     if (i == N) {
       // a complete path: the CRC decides (Section 2.2.5)
+      pk = kNone;
       S.kill(p);
       if constexpr (STATS) ++n_cp;
       const uint32_t row = lane < W ? prow[p] : 0u;
@@ -248,8 +245,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       maxk = kNone;
     }
     wl = i;
-    cand = k0;
-    cand_slot = p;
+    pk = k0;  // slot p now holds the first child
   }
 
   // output: payload = the first K - r information bits of the output path (systematic
