@@ -93,6 +93,9 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   // the path held in the tree: its length when alpha was last computed, its decided bits
   int wl = -1;
   uint32_t ucur = 0u;
+  // after an even leaf wl of the held path: leaf wl + 1's LLR for each value of bit wl, and
+  // the value the first child took (its continuation then needs no tree work)
+  uint32_t g0 = 0u, g1 = 0u, ulast = 0u;
 
   uint32_t fb = 0u, out = 0u;
   bool have_fb = false;
@@ -183,11 +186,15 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       ucur = nu & prefix_mask(lane, i);  // the tree path is zero past its length
     }
     uint32_t a0;
-    if (cont && top <= LY::SMALL) {
-      a0 = cont_dispatch<0, LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+    if (cont && top == 0) {
+      // odd leaf i = wl + 1 continuing: made with leaf wl (leaf_pair)
+      a0 = ulast ? g1 : g0;
+      if constexpr (STATS) ++n_fg;
+    } else if (cont && top <= LY::SMALL) {
+      a0 = cont_dispatch<0, LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg, g0, g1);
     } else {
       if (top >= 6) big_stages<LOGN - 1, LOGN, TR, STATS>(top, i, ucur, root, al, lane, n_fg);
-      a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg);
+      a0 = small_stages<LOGN, TR, STATS>(top, i, ucur, root, al, dummy, lane, n_fg, g0, g1);
     }
 
     // ---- leaf decision and children (eq. scest, eq. PMupd) ---------------------------
@@ -245,6 +252,7 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
       maxk = kNone;
     }
     wl = i;
+    ulast = (info && h) ? 1u : 0u;  // the first child's bit i
     pk = k0;  // slot p now holds the first child
   }
 
@@ -274,8 +282,14 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   }
 }
 
+// Wavefronts per SIMD the register allocation must allow: the one-bank kernels fit 7 (at
+// most 72 VGPRs) and are held to it; the deeper banked stacks keep the compiler's choice.
+template <int NB>
+constexpr int scs_waves_per_simd() { return NB == 1 ? 7 : 1; }
+
 template <int LOGN, class TR, bool STATS, int NB>
-__global__ __launch_bounds__(256) void scs_uniform_kernel(CodeArgs code, int D, int L,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scs_waves_per_simd<NB>())))
+void scs_uniform_kernel(CodeArgs code, int D, int L,
                                                           const typename TR::In* __restrict__ llr,
                                                           int64_t n_frames,
                                                           uint8_t* __restrict__ payload,

@@ -130,13 +130,24 @@ __device__ __forceinline__ void small_chain(uint32_t& x, int start, int i, uint3
   }
 }
 
+// Leaf pair of an even leaf i: its own LLR f(a, b) and, for both values of its bit, the
+// LLR g(a, b, bit) of the odd leaf i + 1 (a, b: the two stage-1 values, in lanes 0 and 1).
+template <class TR>
+__device__ __forceinline__ uint32_t leaf_pair(uint32_t x, uint32_t& g0, uint32_t& g1) {
+  const uint32_t y = xor_lane<1>(x);
+  g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)TR::g(x, y, false));
+  g1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)TR::g(x, y, true));
+  return TR::f(x, y);
+}
+
 // Stages min(top, SMALL) .. 0 in one register; every computed stage above 0 is stored for
-// later leaves.  Returns the leaf LLR (stage 0 is never a parent and is not stored).
+// later leaves.  Returns the leaf LLR (stage 0 is never a parent and is not stored); for an
+// even leaf also the next leaf's LLR for each value of this leaf's bit (leaf_pair).
 template <int LOGN, class TR, bool STATS>
 __device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t u,
                                                  const typename TR::In* __restrict__ root,
                                                  uint32_t* al, uint32_t* dummy, int lane,
-                                                 uint32_t& fg) {
+                                                 uint32_t& fg, uint32_t& g0, uint32_t& g1) {
   constexpr int SM = Layout<LOGN>::SMALL;
   const int start = top < SM ? top : SM;
   const int nin = 2 << start;  // values of stage start + 1, read into lanes < nin
@@ -147,24 +158,25 @@ __device__ __forceinline__ uint32_t small_stages(int top, int i, uint32_t u,
   else
     x = al[nin - 1 + q];
   if (start > 0) small_chain<SM, TR, STATS>(x, start, i, u, al, dummy, lane, fg);
-  x = reg_stage<0, TR>(x, i, u, lane);
+  x = (i & 1) ? reg_stage<0, TR>(x, i, u, lane) : leaf_pair<TR>(x, g0, g1);
   if constexpr (STATS) fg += 1u;
   lds_order();
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-// f-stages LAM .. 1 of a continuing schedule, each stored for later leaves, then stage 0.
+// f-stages LAM .. 1 of a continuing schedule, each stored for later leaves, then stage 0
+// (an even leaf: leaf_pair).
 template <int LAM, class TR, bool STATS>
 __device__ __forceinline__ uint32_t f_chain(uint32_t x, uint32_t* al, uint32_t* dummy, int lane,
-                                            uint32_t& fg) {
+                                            uint32_t& fg, uint32_t& g0, uint32_t& g1) {
   if constexpr (LAM >= 1) {
     x = TR::f(x, xor_lane<(1 << LAM)>(x));
     *(lane < (1 << LAM) ? &al[(1 << LAM) - 1 + lane] : &dummy[lane]) = x;
     if constexpr (STATS) fg += 1u << LAM;
-    return f_chain<LAM - 1, TR, STATS>(x, al, dummy, lane, fg);
+    return f_chain<LAM - 1, TR, STATS>(x, al, dummy, lane, fg, g0, g1);
   } else {
     if constexpr (STATS) fg += 1u;
-    return TR::f(x, xor_lane<1>(x));
+    return leaf_pair<TR>(x, g0, g1);
   }
 }
 
@@ -175,7 +187,7 @@ template <int K, int LOGN, class TR, bool STATS>
 __device__ __forceinline__ uint32_t cont_chain(int i, uint32_t u,
                                                const typename TR::In* __restrict__ root,
                                                uint32_t* al, uint32_t* dummy, int lane,
-                                               uint32_t& fg) {
+                                               uint32_t& fg, uint32_t& g0, uint32_t& g1) {
   constexpr int nin = 2 << K;  // values of stage K + 1
   const int q = lane < nin ? lane : nin - 1;
   uint32_t x;
@@ -188,7 +200,7 @@ __device__ __forceinline__ uint32_t cont_chain(int i, uint32_t u,
   if constexpr (K >= 1) {
     *(lane < (1 << K) ? &al[(1 << K) - 1 + lane] : &dummy[lane]) = x;
     if constexpr (STATS) fg += 1u << K;
-    x = f_chain<K - 1, TR, STATS>(x, al, dummy, lane, fg);
+    x = f_chain<K - 1, TR, STATS>(x, al, dummy, lane, fg, g0, g1);
   } else {
     if constexpr (STATS) fg += 1u;
   }
@@ -200,12 +212,12 @@ template <int K, int LOGN, class TR, bool STATS>
 __device__ __forceinline__ uint32_t cont_dispatch(int top, int i, uint32_t u,
                                                   const typename TR::In* __restrict__ root,
                                                   uint32_t* al, uint32_t* dummy, int lane,
-                                                  uint32_t& fg) {
+                                                  uint32_t& fg, uint32_t& g0, uint32_t& g1) {
   if constexpr (K < Layout<LOGN>::SMALL) {
-    if (top == K) return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg);
-    return cont_dispatch<K + 1, LOGN, TR, STATS>(top, i, u, root, al, dummy, lane, fg);
+    if (top == K) return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg, g0, g1);
+    return cont_dispatch<K + 1, LOGN, TR, STATS>(top, i, u, root, al, dummy, lane, fg, g0, g1);
   } else {
-    return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg);
+    return cont_chain<K, LOGN, TR, STATS>(i, u, root, al, dummy, lane, fg, g0, g1);
   }
 }
 
