@@ -105,6 +105,13 @@ def parse():
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "BENCH_JSON", "OUT_MD"),
                     help="summarise a rocprofv3 --kernel-trace --stats folder of a bench run "
                          "into markdown and exit; runs on the CPU")
+    ap.add_argument("--util-record", nargs=4, metavar=("LDS_DIR", "BUSY_DIR", "BENCH_JSON", "PEAK_JSON"),
+                    help="write the LDS and ALU utilisation record from two rocprofv3 --pmc "
+                         "folders (LDS bandwidth counters; busy and bank-conflict metrics), "
+                         "that run's JSON line and a --lds-peak JSON line, and exit; runs on "
+                         "the CPU")
+    ap.add_argument("--lds-peak", action="store_true",
+                    help="only measure the chip's LDS read bandwidth (project microbenchmark)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args()
@@ -116,19 +123,32 @@ def parse():
 KERNEL_SOURCES = ("paper_1809_03606_amd/csrc/scs_decode.hip", "paper_1809_03606_amd/csrc/scs_device.h",
                   "paper_1809_03606_amd/csrc/scs_tree.h", "paper_1809_03606_amd/csrc/scs_stack.h",
                   "paper_1809_03606_amd/build.py")  # the compiler flags shape the kernel too
+# the other decoders' sources (their kernels share the device headers and the flags)
+_SHARED_SOURCES = ("paper_1809_03606_amd/csrc/scs_device.h", "paper_1809_03606_amd/csrc/scs_tree.h",
+                   "paper_1809_03606_amd/build.py")
+OTHER_SOURCES = {
+    "fsscs": ("paper_1809_03606_amd/csrc/fsscs_decode.hip",
+              "paper_1809_03606_amd/csrc/scs_stack.h") + _SHARED_SOURCES,
+    "scl": ("paper_1809_03606_amd/csrc/scl_decode.hip",) + _SHARED_SOURCES,
+}
+DECODER_KERNELS = {"scs": "scs_uniform_kernel", "fsscs": "fsscs_uniform_kernel",
+                   "scl": "scl_uniform_kernel"}
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "decoder_traffic_n1024.json")
 COUNTERS_RECORD = os.path.join(ROOT, "profiles", "decoder_counters_n1024.json")
+UTIL_RECORD = os.path.join(ROOT, "profiles", "decoder_utilization_n1024.json")
+# LDS: 128 bytes per clock per CU (the data sheet's figure), 256 CUs at 2.4 GHz
+LDS_PEAK_BYTES_PER_S = 128 * 256 * 2.4e9
 CU_CYCLES_PER_S = 256 * 2.4e9  # MI355X: 256 CUs at 2.4 GHz
 
 
-def kernel_source_hash() -> str:
-    """Hash of the decoder's sources with comments and blank lines removed, so that a record
+def kernel_source_hash(decoder: str = "scs") -> str:
+    """Hash of a decoder's sources with comments and blank lines removed, so that a record
     of counters stays valid through comment edits and only a change of code voids it."""
     import hashlib
     import re
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if decoder == "scs" else OTHER_SOURCES[decoder]):
         with open(os.path.join(ROOT, f)) as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).strip()
@@ -137,15 +157,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(frames_per_launch: int):
+def traffic_record_path(decoder: str = "scs") -> str:
+    if decoder == "scs":
+        return TRAFFIC_RECORD
+    return os.path.join(ROOT, "profiles", "%s_traffic_n1024.json" % decoder)
+
+
+def measured_traffic(frames_per_launch: int, decoder: str = "scs"):
     """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE counters, or None when
     the record is missing or was taken on different kernel sources."""
     try:
-        with open(TRAFFIC_RECORD) as fh:
+        with open(traffic_record_path(decoder)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(decoder):
         return None
     return rec["hbm_bytes_per_frame"] * frames_per_launch
 
@@ -173,9 +199,134 @@ def issue_bound(per_point, frames):
             "cu_cycles_per_extension": cycles, "frac": salu / cycles, "at_ebn0_db": 2.0}
 
 
+def lds_peak():
+    """The LDS read rate of the whole chip with conflict-free 16-byte and 4-byte reads per
+    lane (libldspeak.so, a microbenchmark built beside the decoder library)."""
+    import ctypes
+
+    from paper_1809_03606_amd import build
+
+    if not os.path.exists(build.LDS_PEAK_LIB):
+        raise SystemExit("bench.py: %s is not built (python -m paper_1809_03606_amd.build)"
+                         % build.LDS_PEAK_LIB)
+    lib = ctypes.CDLL(build.LDS_PEAK_LIB)
+    lib.lds_peak_measure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    res = {}
+    for width in (16, 4):
+        bps, ms = ctypes.c_double(), ctypes.c_double()
+        rc = lib.lds_peak_measure(width, 5, ctypes.byref(bps), ctypes.byref(ms))
+        if rc != 0:
+            raise SystemExit("bench.py: lds_peak_measure(%d) failed: %d" % (width, rc))
+        res["read_%dB_per_lane" % width] = {"bytes_per_s": bps.value, "launch_ms": ms.value}
+        log("LDS reads of %d B per lane: %.2f TB/s (%.3f ms per launch)"
+            % (width, bps.value / 1e12, ms.value))
+    res["nominal_bytes_per_s"] = LDS_PEAK_BYTES_PER_S
+    print(json.dumps({"lds_peak": res}))
+
+
+def _counter_totals(folder: str, exclude: str = ", true"):
+    """Per-counter values of the timed decoder launch in a rocprofv3 --pmc folder: raw
+    counters summed over their rows, derived metrics (one row per dispatch) averaged."""
+    tot, rows = {}, {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        name = r["Kernel_Name"]
+        if DECODER in name and exclude not in name:
+            c = r["Counter_Name"]
+            tot[c] = tot.get(c, 0.0) + float(r["Counter_Value"])
+            rows[c] = rows.get(c, 0) + 1
+    return tot, rows
+
+
+def write_util_record(lds_dir, busy_dir, bench_json, peak_json):
+    """LDS bytes per path extension (SQ_INSTS_LDS_{LOAD,STORE,ATOMIC}_BANDWIDTH, 64-byte
+    units), LDS, vector and scalar busy fractions and vector lane use of the timed 2 dB SCS
+    launch of `bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 --cpu-sample 0
+    --latency-requests 0`,
+    beside the LDS rate measured by `bench.py --lds-peak`."""
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    with open(peak_json) as fh:
+        pk = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])["lds_peak"]
+    lds, _ = _counter_totals(lds_dir)
+    busy, nrows = _counter_totals(busy_dir)
+    derived = {k: busy[k] / nrows[k] for k in ("VALUBusy", "SALUBusy", "VALUUtilization",
+                                               "LDSBankConflict") if k in busy}
+    if "LdsUtil" in lds:
+        _, lrows = _counter_totals(lds_dir)
+        derived["LdsUtil"] = lds["LdsUtil"] / lrows["LdsUtil"]
+    p = b["per_point"]["2.0"]
+    ext = p["mean_iterations"] * b["config"]["frames_per_point"]
+    parts = {k: lds.get("SQ_INSTS_LDS_%s_BANDWIDTH" % k, 0.0) * 64.0
+             for k in ("LOAD", "STORE", "ATOMIC")}
+    total = sum(parts.values())
+    secs = p["launch_ms"] * 1e-3
+    rec = {
+        "kernel": DECODER + "<10,f32> (64 lanes per frame, one stack bank)",
+        "kernel_source_hash": kernel_source_hash(),
+        "workload": "PC(1024,512)+CRC16, D=32, L=8, Eb/N0 2.0 dB, %d frames"
+                    % b["config"]["frames_per_point"],
+        "commands": [
+            "rocprofv3 --pmc SQ_INSTS_LDS_LOAD_BANDWIDTH SQ_INSTS_LDS_STORE_BANDWIDTH "
+            "SQ_INSTS_LDS_ATOMIC_BANDWIDTH LdsUtil --output-format csv -d <dir> -o run -- python "
+            "bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 --cpu-sample 0 "
+            "--latency-requests 0",
+            "rocprofv3 --pmc VALUBusy SALUBusy VALUUtilization LDSBankConflict --output-format csv "
+            "-d <dir> -o run -- python bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 "
+            "--cpu-sample 0 --latency-requests 0",
+            "python bench.py --lds-peak",
+            "python bench.py --util-record <lds dir> <busy dir> <bench json> <lds-peak json>"],
+        "extensions": ext,
+        "lds_bytes": parts,
+        "lds_bytes_per_extension": total / ext,
+        "lds_bytes_per_s_in_profiled_run": total / secs,
+        "profiled_launch_ms": p["launch_ms"],
+        "derived_pct": derived,
+        "lds_peak": pk,
+    }
+    with open(UTIL_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"util_record": UTIL_RECORD, "lds_bytes_per_extension": rec["lds_bytes_per_extension"],
+                      "derived_pct": derived}))
+
+
+def rocprof_use(per_point, frames):
+    """The SCS kernel at 2 dB against the chip's vector-ALU and LDS peaks, from the recorded
+    counters (vector instructions per path extension and their lane use; LDS bytes per
+    extension) times this run's path extensions per second.  The LDS peak is the one
+    `bench.py --lds-peak` measured.  None without both records taken on the current kernel
+    sources or without a 2 dB point."""
+    recs = []
+    for path in (COUNTERS_RECORD, UTIL_RECORD):
+        try:
+            with open(path) as fh:
+                recs.append(json.load(fh))
+        except (OSError, ValueError):
+            return None
+    if any(r.get("kernel_source_hash") != kernel_source_hash() for r in recs) or 2.0 not in per_point:
+        return None
+    sq, util = recs
+    p = per_point[2.0]
+    if not frames or not p.get("mean_iterations"):
+        return None
+    ext_per_s = frames * p["mean_iterations"] / (p["launch_ms"] * 1e-3)
+    lanes = util["derived_pct"]["VALUUtilization"] / 100.0 * 64.0
+    valu = sq["per_extension"]["SQ_INSTS_VALU"] * lanes * ext_per_s
+    lds = util["lds_bytes_per_extension"] * ext_per_s
+    meas = util["lds_peak"]["read_16B_per_lane"]["bytes_per_s"]
+    return {"at_ebn0_db": 2.0, "extensions_per_s": ext_per_s,
+            "valu_lane_ops_per_s": valu, "valu_peak": PEAK_LANE_OPS, "valu_frac": valu / PEAK_LANE_OPS,
+            "valu_insts_per_extension": sq["per_extension"]["SQ_INSTS_VALU"],
+            "valu_active_lanes": lanes,
+            "lds_bytes_per_s": lds, "lds_bytes_per_extension": util["lds_bytes_per_extension"],
+            "lds_peak_measured": meas, "lds_frac_measured": lds / meas,
+            "lds_peak_nominal": LDS_PEAK_BYTES_PER_S, "busy_pct": util["derived_pct"]}
+
+
 def write_counters_record(sq_dir, bench_json):
     """Instructions per path extension of the timed SCS launch from a rocprofv3 --pmc SQ_*
-    folder of `bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 --cpu-sample 0`."""
+    folder of `bench.py --frames 100000 --points 2.0 --steps 1 --warmup 0 --cpu-sample 0
+    --latency-requests 0`."""
     with open(bench_json) as fh:
         b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
     agg = {}
@@ -193,7 +344,7 @@ def write_counters_record(sq_dir, bench_json):
         "command": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
                    "SQ_INSTS_SMEM SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_BRANCH --output-format csv "
                    "-d <dir> -o run -- python bench.py --frames 100000 --points 2.0 --steps 1 "
-                   "--warmup 0 --cpu-sample 0",
+                   "--warmup 0 --cpu-sample 0 --latency-requests 0",
         "extensions": ext,
         "totals": agg,
         "per_extension": {k: v / ext for k, v in agg.items()},
@@ -229,32 +380,36 @@ def _counter_kib(folder: str, counter: str, kernel: str, exclude: str = "\0"):
     return [per[k] for k in sorted(per, key=int)]
 
 
-def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_000_000):
+def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_000_000,
+                         decoder: str = "scs"):
     """HBM bytes per decoder launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each
     scaled by what the same counter reads for a device copy of COPY_BYTES."""
+    kernel = DECODER_KERNELS[decoder]
     # the timed launch only: the counter launch (the ", true" variant) also writes statistics
-    dec_f = _counter_kib(fetch_dir, "FETCH_SIZE", DECODER, ", true")
-    dec_w = _counter_kib(write_dir, "WRITE_SIZE", DECODER, ", true")
+    dec_f = _counter_kib(fetch_dir, "FETCH_SIZE", kernel, ", true")
+    dec_w = _counter_kib(write_dir, "WRITE_SIZE", kernel, ", true")
     cp_f = max(_counter_kib(cfetch_dir, "FETCH_SIZE", "copyBuffer"))  # the device copy
     cp_w = max(_counter_kib(cwrite_dir, "WRITE_SIZE", "copyBuffer"))
     ff = COPY_BYTES / (cp_f * 1024.0)
     wf = COPY_BYTES / (cp_w * 1024.0)
     rd = float(np.mean(dec_f)) * 1024.0 * ff
     wr = float(np.mean(dec_w)) * 1024.0 * wf
+    flag = "" if decoder == "scs" else "--decoder %s " % decoder
     rec = {
-        "kernel": DECODER + "<10,f32> (64 lanes per frame)",
-        "kernel_source_hash": kernel_source_hash(),
-        "workload": "PC(1024,512)+CRC16, D=32, L=8, Eb/N0 2.0 dB, %d frames per launch" % frames,
+        "kernel": kernel + "<10,f32> (64 lanes per frame)",
+        "kernel_source_hash": kernel_source_hash(decoder),
+        "workload": "PC(1024,512)+CRC16, %s, Eb/N0 2.0 dB, %d frames per launch"
+                    % ("list L=8" if decoder == "scl" else "D=32, L=8", frames),
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
-            "--points 2.0 --steps 1 --warmup 0 --cpu-sample 0",
+            "%s--points 2.0 --steps 1 --warmup 0 --cpu-sample 0 --latency-requests 0" % flag,
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python bench.py "
-            "--points 2.0 --steps 1 --warmup 0 --cpu-sample 0",
+            "%s--points 2.0 --steps 1 --warmup 0 --cpu-sample 0 --latency-requests 0" % flag,
             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
             "--calibrate-copy %d" % COPY_BYTES,
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python bench.py "
             "--calibrate-copy %d" % COPY_BYTES,
-            "python bench.py --traffic-record <fetch> <write> <copy fetch> <copy write>"],
+            "python bench.py %s--traffic-record <fetch> <write> <copy fetch> <copy write>" % flag],
         "raw_kib_per_dispatch": {"decoder_fetch_size": dec_f, "decoder_write_size": dec_w,
                                  "copy_1GiB_fetch_size": cp_f, "copy_1GiB_write_size": cp_w},
         "calibration": {"fetch_factor": ff, "write_factor": wf,
@@ -265,14 +420,16 @@ def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_
         "hbm_bytes_per_frame": (rd + wr) / frames,
         "algorithmic_bytes_per_frame": 4 * N + (K - CRC) + 1,
     }
-    with open(TRAFFIC_RECORD, "w") as fh:
+    path = traffic_record_path(decoder)
+    with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
-    print(json.dumps({"traffic_record": TRAFFIC_RECORD, "hbm_bytes_per_frame": rec["hbm_bytes_per_frame"]}))
+    print(json.dumps({"traffic_record": path, "hbm_bytes_per_frame": rec["hbm_bytes_per_frame"]}))
 
 
 def write_trace_summary(trace_dir, bench_json, out_md):
-    """Markdown summary of a kernel trace of `python bench.py --cpu-sample 0`: per-kernel
-    statistics, and the decoder's mean duration beside bench.py's own HIP-event mean."""
+    """Markdown summary of a kernel trace of `python bench.py --cpu-sample 0
+    --latency-requests 0`: per-kernel statistics, and the decoder's mean duration beside
+    bench.py's own HIP-event mean."""
     rows = _csv_rows(trace_dir, "kernel_trace.csv")
     with open(bench_json) as fh:
         b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
@@ -296,11 +453,12 @@ def write_trace_summary(trace_dir, bench_json, out_md):
     lines = ["# Kernel trace: %s decoder, PC(1024,512)+CRC-16 sweep" % title, "",
              "Command (from the repository root on one MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
-             "python bench.py%s --cpu-sample 0" % extra, "",
+             "python bench.py%s --cpu-sample 0 --latency-requests 0" % extra, "",
              "Workload: N=1024, K=512 (496 payload + 16 CRC), %s, Eb/N0 1.0/1.5/2.0/2.5/3.0 "
              "dB, %d frames per point, launch shape %s.  Decoder launches: one counter launch "
              "per point (stats variant), %d warmup and %d timed steps of one launch per point.  "
-             "The CPU-oracle sample is off so that its small launches do not enter the average."
+             "The CPU-oracle sample and the request-latency probe are off so that their small "
+             "launches do not enter the average."
              % (("list of L=%d" % b["config"]["L"]) if decoder.startswith("scl") else
                 ("D=%d, L=%d" % (b["config"]["D"], b["config"]["L"])),
                 b["config"]["frames_per_point"], b["config"].get("launch_shape"), b["warmup"],
@@ -341,7 +499,15 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.traffic_record:
-        write_traffic_record(*args.traffic_record)
+        if args.decoder == "fssc":
+            raise SystemExit("bench.py: traffic records are taken for scs, fsscs and scl")
+        write_traffic_record(*args.traffic_record, decoder=args.decoder)
+        return
+    if args.util_record:
+        write_util_record(*args.util_record)
+        return
+    if args.lds_peak:
+        lds_peak()
         return
     if args.counters_record:
         write_counters_record(*args.counters_record)
@@ -524,17 +690,20 @@ def main():
     mean_launch_s = float(all_ms.mean()) * 1e-3
     achieved = ops_per_launch / mean_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    # the counter records were taken on the binary32 SCS kernel at 64 lanes per frame, on
-    # the headline configuration
-    recorded = (not fast and not scl and args.dtype == "f32"
-                and (D, L) == HEADLINE_DL)
+    # the counter records were taken on the binary32 kernels on the headline configuration
+    # (traffic: each decoder; instruction and LDS counts: the SCS kernel)
+    headline = args.dtype == "f32" and (D, L) == HEADLINE_DL
+    recorded = headline and not fast and not scl
+    dec_name = "scl" if scl else "fsscs" if fast else "scs"
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                "frac": achieved / peak, "traffic": measured_traffic(B) if recorded else None,
+                "frac": achieved / peak,
+                "traffic": measured_traffic(B, dec_name) if headline else None,
                 "kernel": ("fsscs_uniform_kernel" if fast else "scl_uniform_kernel" if scl else
                            "scs_uniform_kernel")
                           + ("<10,f32>" if args.dtype == "f32" else "<10,i8>"),
                 "mean_launch_ms": float(all_ms.mean()), "ops_per_launch": ops_per_launch,
-                "issue": issue_bound(per_point, B) if recorded else None}
+                "issue": issue_bound(per_point, B) if recorded else None,
+                "rocprof": rocprof_use(per_point, B) if recorded else None}
 
     # -- CPU oracle on a bounded sample of the same frames -----------------------------
     cpu = None

@@ -15,6 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpolarscs.so")
+# the LDS bandwidth microbenchmark (a measurement aid, not part of the decoder library)
+LDS_PEAK_LIB = os.path.join(PKG, "libldspeak.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -44,15 +46,20 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs)
+    os.replace(tmp, lib)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs)
-    os.replace(tmp, LIB)
+    with ThreadPoolExecutor(len(SOURCES) + 1) as ex:
+        objs = list(ex.map(_compile, SOURCES + ["lds_peak.hip"]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], LDS_PEAK_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, LDS_PEAK_LIB)
     return LIB
 
 

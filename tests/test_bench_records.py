@@ -90,3 +90,58 @@ def test_sweep_config_bounds_and_headline(monkeypatch):
             bench.sweep_config(*bad)
     bench.sweep_config(128, 4)
     assert (bench.D, bench.L) == (128, 4)
+
+
+def _write_csv(folder, rows):
+    folder.mkdir(parents=True)
+    with open(folder / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+
+
+def test_util_record_and_rocprof_figures(sources, tmp_path, monkeypatch):
+    """LDS bytes per extension from the 64-byte bandwidth counters of the timed launch only,
+    derived metrics taken as reported, and the live figures: recorded per-extension work
+    times this run's extensions per second."""
+    timed, stats = "void scs_uniform_kernel<10, TrF32, false, 1>(x)", "void scs_uniform_kernel<10, TrF32, true, 1>(x)"
+    lds_rows, busy_rows = [], []
+    for kernel, scale in ((timed, 1.0), (stats, 7.0)):
+        for c, v in (("SQ_INSTS_LDS_LOAD_BANDWIDTH", 1000.0), ("SQ_INSTS_LDS_STORE_BANDWIDTH", 500.0),
+                     ("SQ_INSTS_LDS_ATOMIC_BANDWIDTH", 250.0), ("LdsUtil", 20.0)):
+            lds_rows.append({"Kernel_Name": kernel, "Counter_Name": c, "Counter_Value": v * scale,
+                             "Dispatch_Id": len(lds_rows)})
+        for c, v in (("VALUBusy", 80.0), ("SALUBusy", 75.0), ("VALUUtilization", 50.0),
+                     ("LDSBankConflict", 2.0)):
+            busy_rows.append({"Kernel_Name": kernel, "Counter_Name": c, "Counter_Value": v * scale,
+                              "Dispatch_Id": len(busy_rows)})
+    _write_csv(tmp_path / "lds" / "run", lds_rows)
+    _write_csv(tmp_path / "busy" / "run", busy_rows)
+    line = {"config": {"frames_per_point": 10},
+            "per_point": {"2.0": {"mean_iterations": 7.0, "launch_ms": 1.0}}}
+    bj = tmp_path / "bench.json"
+    bj.write_text(json.dumps(line) + "\n")
+    pk = tmp_path / "peak.json"
+    pk.write_text(json.dumps({"lds_peak": {"read_16B_per_lane": {"bytes_per_s": 1e12, "launch_ms": 1.0},
+                                           "read_4B_per_lane": {"bytes_per_s": 5e11, "launch_ms": 1.0},
+                                           "nominal_bytes_per_s": 7.8e13}}) + "\n")
+    util = tmp_path / "util.json"
+    counters = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "UTIL_RECORD", str(util))
+    monkeypatch.setattr(bench, "COUNTERS_RECORD", str(counters))
+    bench.write_util_record(str(tmp_path / "lds"), str(tmp_path / "busy"), str(bj), str(pk))
+    rec = json.loads(util.read_text())
+    assert rec["lds_bytes_per_extension"] == pytest.approx(1750.0 * 64 / 70.0)
+    assert rec["derived_pct"] == {"VALUBusy": 80.0, "SALUBusy": 75.0, "VALUUtilization": 50.0,
+                                  "LDSBankConflict": 2.0, "LdsUtil": 20.0}
+    assert bench.rocprof_use({2.0: {"mean_iterations": 100.0, "launch_ms": 2.0}}, 1000) is None
+    counters.write_text(json.dumps({"kernel_source_hash": bench.kernel_source_hash(),
+                                    "per_extension": {"SQ_INSTS_SALU": 60.0, "SQ_INSTS_VALU": 40.0}}))
+    got = bench.rocprof_use({2.0: {"mean_iterations": 100.0, "launch_ms": 2.0}}, 1000)
+    ext_per_s = 1000 * 100.0 / 2e-3
+    assert got["extensions_per_s"] == pytest.approx(ext_per_s)
+    assert got["valu_lane_ops_per_s"] == pytest.approx(40.0 * 32.0 * ext_per_s)
+    assert got["lds_bytes_per_s"] == pytest.approx(1600.0 * ext_per_s)
+    assert got["lds_frac_measured"] == pytest.approx(1600.0 * ext_per_s / 1e12)
+    sources.write_text("int f() {\n  return 4;\n}\n")
+    assert bench.rocprof_use({2.0: {"mean_iterations": 100.0, "launch_ms": 2.0}}, 1000) is None
