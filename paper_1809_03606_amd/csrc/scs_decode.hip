@@ -47,14 +47,24 @@
 namespace {
 
 // One frame, one wavefront.  `lds` is this wave's private region of
-// lds_words_per_wave(N, D) words.
-template <int LOGN, class TR, bool STATS, int NB = 1>
+// scs_lds_words_per_wave(N, D) words.
+// PERSISTENT: called once per frame inside the persistent loop of the mixed kernel, which
+// inlines one copy per code length.
+template <int LOGN, class TR, bool STATS, int NB = 1, bool PERSISTENT = false>
 __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJob& job,
                                              uint32_t* lds) {
   using LY = Layout<LOGN>;
   constexpr int N = LY::N;
   constexpr int W = LY::W;
-  const int lane = lane_id();
+  int lane = lane_id();
+  if constexpr (PERSISTENT) {
+    // A value the compiler cannot see through (an empty asm statement, no instruction):
+    // nothing derived from the lane number (masks, LDS addresses) is hoisted out of the
+    // persistent loop, where it would stay live for every code length at once; this takes
+    // the mixed kernel from 162 to 88 VGPRs.
+    asm volatile("" : "+v"(lane));
+    __builtin_assume(lane >= 0 && lane < kWave);
+  }
   const int D = job.D, L = job.L;
   const bool use_crc = code.crc != 0;
   const typename TR::In* __restrict__ root = (const typename TR::In*)job.llr;
@@ -69,8 +79,8 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
   // 0 needs no store.  The empty path's row starts at zero.
   prow[0] = 0u;
   uint32_t* cnt32 = lds;               // N bytes: extensions per length
-  uint32_t* al = cnt32 + (N + 3) / 4;  // N - 1 words: alpha stages 0 .. n-1
-  uint32_t* dummy = al + N;            // kWave words: stores of lanes that must not store
+  uint32_t* al = cnt32 + (N + 3) / 4;  // alpha stages 0 .. n-1 (0 .. n-2 without KEEP_TOP)
+  uint32_t* dummy = al + LY::ALPHA_WORDS;  // kWave words: stores of lanes that must not store
 
   const uint32_t infow = lane < W ? code.info[lane] : 0u;
   for (int j = lane; j < (N + 3) / 4; j += kWave) cnt32[j] = 0u;
@@ -319,17 +329,17 @@ template <class TR, bool STATS>
 __device__ __forceinline__ void decode_any(int logn, const CodeArgs& code, const FrameJob& job,
                                            uint32_t* lds) {
   switch (logn) {
-    case 1: decode_frame<1, TR, STATS>(code, job, lds); break;
-    case 2: decode_frame<2, TR, STATS>(code, job, lds); break;
-    case 3: decode_frame<3, TR, STATS>(code, job, lds); break;
-    case 4: decode_frame<4, TR, STATS>(code, job, lds); break;
-    case 5: decode_frame<5, TR, STATS>(code, job, lds); break;
-    case 6: decode_frame<6, TR, STATS>(code, job, lds); break;
-    case 7: decode_frame<7, TR, STATS>(code, job, lds); break;
-    case 8: decode_frame<8, TR, STATS>(code, job, lds); break;
-    case 9: decode_frame<9, TR, STATS>(code, job, lds); break;
-    case 10: decode_frame<10, TR, STATS>(code, job, lds); break;
-    case 11: decode_frame<11, TR, STATS>(code, job, lds); break;
+    case 1: decode_frame<1, TR, STATS, 1, true>(code, job, lds); break;
+    case 2: decode_frame<2, TR, STATS, 1, true>(code, job, lds); break;
+    case 3: decode_frame<3, TR, STATS, 1, true>(code, job, lds); break;
+    case 4: decode_frame<4, TR, STATS, 1, true>(code, job, lds); break;
+    case 5: decode_frame<5, TR, STATS, 1, true>(code, job, lds); break;
+    case 6: decode_frame<6, TR, STATS, 1, true>(code, job, lds); break;
+    case 7: decode_frame<7, TR, STATS, 1, true>(code, job, lds); break;
+    case 8: decode_frame<8, TR, STATS, 1, true>(code, job, lds); break;
+    case 9: decode_frame<9, TR, STATS, 1, true>(code, job, lds); break;
+    case 10: decode_frame<10, TR, STATS, 1, true>(code, job, lds); break;
+    case 11: decode_frame<11, TR, STATS, 1, true>(code, job, lds); break;
     default: break;
   }
 }
@@ -338,17 +348,20 @@ __device__ __forceinline__ void decode_any(int logn, const CodeArgs& code, const
 // captured in a graph without memset nodes).
 __global__ void reset_counter_kernel(uint32_t* counter) { *counter = 0u; }
 
+// At most 80 VGPRs (6 wavefronts per SIMD): measured faster than the unconstrained 88 (5 per
+// SIMD) and than 72 (7 per SIMD, which spills).
 template <class TR, bool STATS>
-__global__ __launch_bounds__(256) void scs_mixed_kernel(const CodeArgs* __restrict__ codes,
-                                                        const scs_frame* __restrict__ frames,
-                                                        const int32_t* __restrict__ order,
-                                                        uint32_t n_frames,
-                                                        const typename TR::In* __restrict__ llr,
-                                                        uint8_t* __restrict__ payload,
-                                                        uint8_t* __restrict__ status,
-                                                        scs_stats* __restrict__ stats,
-                                                        uint32_t* __restrict__ counter,
-                                                        int wave_words) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void scs_mixed_kernel(const CodeArgs* __restrict__ codes,
+                      const scs_frame* __restrict__ frames,
+                      const int32_t* __restrict__ order,
+                      uint32_t n_frames,
+                      const typename TR::In* __restrict__ llr,
+                      uint8_t* __restrict__ payload,
+                      uint8_t* __restrict__ status,
+                      scs_stats* __restrict__ stats,
+                      uint32_t* __restrict__ counter,
+                      int wave_words) {
   extern __shared__ uint32_t lds[];
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
@@ -466,7 +479,7 @@ UniformKernel<TR> uniform_kernel_for(int logn, bool stats, int nb) {
 }
 
 int waves_per_block(int N, int D) {
-  const int bytes = lds_words_per_wave(N, D) * 4;
+  const int bytes = scs_lds_words_per_wave(N, D) * 4;
   int wpb = 4;
   while (wpb > 1 && wpb * bytes > 64 * 1024) wpb >>= 1;
   return wpb;
@@ -671,7 +684,7 @@ int scs_decode_batch(scs_ctx* ctx, const polar_code* code, int32_t D, int32_t L,
   hipStream_t s = (hipStream_t)hip_stream;
   int wpb = waves_per_block(code->N, D);
   if (ctx->wpb && ctx->wpb < wpb) wpb = ctx->wpb;
-  const int wave_words = lds_words_per_wave(code->N, D);
+  const int wave_words = scs_lds_words_per_wave(code->N, D);
   const size_t lds = (size_t)wpb * wave_words * 4;
   const int64_t blocks = (n_frames + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return POLAR_EUNSUPPORTED;
@@ -797,7 +810,7 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
     if (d.code < 0 || d.code >= n_codes || d.D < 1 || d.D > 64 || d.L < 1 || d.L > 255 ||
         d._pad != 0 || d.llr_off < 0 || d.out_off < 0)
       return POLAR_EINVAL;
-    wave_words = std::max(wave_words, lds_words_per_wave(codes[d.code]->N, d.D));
+    wave_words = std::max(wave_words, scs_lds_words_per_wave(codes[d.code]->N, d.D));
   }
   if ((size_t)wave_words * 4 > 64 * 1024) return POLAR_EUNSUPPORTED;
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -946,7 +959,7 @@ int scs_decode_mixed_noalloc(scs_ctx* ctx, const polar_code* const* codes, int32
         d._pad != 0 || d.llr_off < 0 || d.out_off < 0)
       return POLAR_EINVAL;
     used[d.code] = true;
-    wave_words = std::max(wave_words, lds_words_per_wave(codes[d.code]->N, d.D));
+    wave_words = std::max(wave_words, scs_lds_words_per_wave(codes[d.code]->N, d.D));
   }
   if ((size_t)wave_words * 4 > kMaxLdsPerBlock) return POLAR_EUNSUPPORTED;
   // scratch layout: work counter | code tables | CRC syndrome tables | frame descriptors

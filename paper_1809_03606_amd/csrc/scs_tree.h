@@ -12,11 +12,19 @@ namespace {
 // alpha tree in LDS: stage lambda (Lambda = 2^lambda values) at word offset Lambda - 1,
 // stages 0 .. n-1 (N - 1 words); the channel LLRs (stage n) are read from the input.
 // ------------------------------------------------------------------------------------
+// From this code length up (N = 1024) the SCS decoder does not keep stage n-1 (N/2 words):
+// stage n-2 is computed straight from the channel LLRs whenever it is needed, which halves
+// the alpha tree's share of LDS and lets more wavefronts share a CU (measured: N = 2048
+// +13 %, N = 1024 +2 %, shorter codes not measurably different).
+constexpr int kTopFreeLogN = 10;
+
 template <int LOGN>
 struct Layout {
   static constexpr int N = 1 << LOGN;
   static constexpr int W = N >= 32 ? N / 32 : 1;         // 32-bit words per bit vector
   static constexpr int SMALL = LOGN < 6 ? LOGN - 1 : 5;  // highest stage kept lane-parallel
+  static constexpr bool KEEP_TOP = LOGN < kTopFreeLogN;  // stage n-1 kept in LDS
+  static constexpr int ALPHA_WORDS = KEEP_TOP ? N : N / 2;  // stages kept (+1 spare word)
 };
 
 constexpr uint32_t kLowMask[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
@@ -58,6 +66,50 @@ __device__ __forceinline__ uint32_t sibling_big(uint32_t u, int base, int lane) 
   return x;
 }
 
+// Bit e = 64 r + lane of a lane-per-word partial-sum vector bx (sibling_big) whose block
+// starts at word w0 (the vector's bits 32 w0 + 64 r .. + 63 belong to chunk r).
+__device__ __forceinline__ bool chunk_bit(uint32_t bx, int w0, int r, int lane) {
+  const uint32_t mlo = readlane(bx, w0 + 2 * r), mhi = readlane(bx, w0 + 2 * r + 1);
+  const uint32_t m = lane < 32 ? mlo : mhi;
+  return (m >> (lane & 31)) & 1u;
+}
+
+// Stage n-2 of a code whose stage n-1 is not kept (Layout::KEEP_TOP false): value e of
+// stage n-2 from values e and e + N/4 of stage n-1, each made on the spot from the channel
+// LLRs x and x + N/2 (eq. llrcalc twice; the same operations on the same operands as when
+// stage n-1 is stored, so the values are identical).
+template <int LOGN, class TR, bool STATS>
+__device__ __forceinline__ void top_two_stages(int i, uint32_t u,
+                                               const typename TR::In* __restrict__ root,
+                                               uint32_t* al, int lane, uint32_t& fg) {
+  constexpr int L1 = LOGN - 1, L2 = LOGN - 2;
+  constexpr int Lam1 = 1 << L1, Lam2 = 1 << L2;
+  const bool odd1 = (i >> L1) & 1;                 // stage n-1: g-node (right half)
+  const bool odd2 = (i >> L2) & 1;                 // stage n-2: g-node
+  const int base2 = ((i >> L2) - 1) << L2;         // its left sibling block
+  uint32_t b1 = 0u, b2 = 0u;
+  if (odd1) b1 = sibling_big<L1>(u, 0, lane);      // partial sums of bits [0, N/2)
+  if (odd2) b2 = sibling_big<L2>(u, base2, lane);
+  uint32_t* dst = al + (Lam2 - 1);
+#pragma unroll
+  for (int r = 0; r < Lam2 / kWave; ++r) {
+    const int e = r * kWave + lane;
+    const uint32_t a0 = TR::load(root, e), a1 = TR::load(root, e + Lam1);
+    const uint32_t c0 = TR::load(root, e + Lam2), c1 = TR::load(root, e + Lam2 + Lam1);
+    uint32_t p0, p1;
+    if (odd1) {
+      p0 = TR::g(a0, a1, chunk_bit(b1, 0, r, lane));
+      p1 = TR::g(c0, c1, chunk_bit(b1, 0, r + Lam2 / kWave, lane));
+    } else {
+      p0 = TR::f(a0, a1);
+      p1 = TR::f(c0, c1);
+    }
+    dst[e] = odd2 ? TR::g(p0, p1, chunk_bit(b2, base2 >> 5, r, lane)) : TR::f(p0, p1);
+  }
+  if constexpr (STATS) fg += (uint32_t)(Lam1 + Lam2);
+  lds_order();
+}
+
 // Stage LAM >= 6 (Lambda >= 64), then the stages below it down to 6: value e = 64 r + lane
 // of stage lambda from values e and e + Lambda of its parent (eq. llrcalc): f for even
 // phi = i >> lambda, g for odd phi with the partial sums of the left sibling block.
@@ -65,7 +117,11 @@ template <int LAM, int LOGN, class TR, bool STATS>
 __device__ __forceinline__ void big_stages(int top, int i, uint32_t u,
                                            const typename TR::In* __restrict__ root,
                                            uint32_t* al, int lane, uint32_t& fg) {
-  if constexpr (LAM >= 6) {
+  if constexpr (LAM + 1 == LOGN && !Layout<LOGN>::KEEP_TOP) {
+    static_assert(LAM - 1 >= 6, "stage n-2 must be a wide stage");
+    if (LAM - 1 <= top) top_two_stages<LOGN, TR, STATS>(i, u, root, al, lane, fg);
+    big_stages<LAM - 2, LOGN, TR, STATS>(top, i, u, root, al, lane, fg);
+  } else if constexpr (LAM >= 6) {
     if (LAM <= top) {
       constexpr int Lam = 1 << LAM;
       const bool odd = (i >> LAM) & 1;
@@ -233,6 +289,12 @@ struct FrameJob {
 // rows of the stack live in lane-private memory (see decode_frame), so the LDS share of a
 // frame does not depend on D.
 inline int lds_words_per_wave(int N, int /*D*/) { return (N + 3) / 4 + N + kWave; }
+
+// The same for the SCS decoder, which keeps only stages 0 .. n-2 from N = 2^kTopFreeLogN up
+// (Layout::ALPHA_WORDS): 3.3 KB per frame at N = 1024, 6.3 KB at N = 2048.
+inline int scs_lds_words_per_wave(int N, int /*D*/) {
+  return (N + 3) / 4 + (N >= (1 << kTopFreeLogN) ? N / 2 : N) + kWave;
+}
 
 constexpr int kMaxD = 64;  // stack slots are lanes
 

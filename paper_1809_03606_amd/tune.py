@@ -76,7 +76,7 @@ def save(entries: dict, path: str | None = None):
     os.replace(tmp, path)
 
 
-def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames: int = 65536,
+def tune(code, D: int, L: int, dtype: str = "f32", ebn0_db: float = 2.0, frames: int = 262144,
          reps: int = 2, seed: int = 7, path: str | None = None, verbose: bool = False,
          decoder: str = "scs") -> dict:
     """Time every launch shape on `frames` noisy frames (for the list decoder at L < 8,
@@ -230,7 +230,7 @@ def main(argv=None):
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--dtype", choices=("f32", "i8"), default="f32")
     ap.add_argument("--ebn0", type=float, default=2.0)
-    ap.add_argument("--frames", type=int, default=65536)
+    ap.add_argument("--frames", type=int, default=262144)
     ap.add_argument("--decoder", choices=("scs", "fsscs", "scl"), default="scs")
     ap.add_argument("--out", default=None, help="cache file (default: the user cache)")
     a = ap.parse_args(argv)
