@@ -515,6 +515,13 @@ def main():
     if args.trace_summary:
         write_trace_summary(*args.trace_summary)
         return
+    if args.workload == "serve":
+        # The serving slots run their batches side by side only from separate hardware queues:
+        # HIP maps streams beyond its queue count (GPU_MAX_HW_QUEUES, 4 by default) onto shared
+        # queues, whose launches run one after another.  Four slots plus the default and the
+        # input-generation streams need more than 4 (set before HIP starts).
+        if int(os.environ.get("GPU_MAX_HW_QUEUES") or 4) < 8:
+            os.environ["GPU_MAX_HW_QUEUES"] = "8"
     if args.workload in ("mixed", "serve"):
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
@@ -1108,6 +1115,14 @@ def run_depth(args):
     print(json.dumps(line))
 
 
+# Device-memory budget of the serving run's admission: a request's footprint counts its
+# LLRs, its outputs and, for every frame, a decoder state as if the frame were resident
+# (stack rows of D slots, L counters, alpha tree; serve.request_footprint), about 12 KB per
+# frame of the mixed distribution; 16 GiB (of the MI355X's 288) lets the four slots' full
+# batches of 16,384 frames be in flight together.
+SERVE_BUDGET = 16 << 30
+
+
 def serve_pool(seed, n_req, codes, pcs, on_device=True):
     """A pool of requests of the mixed distribution (code, D, Eb/N0 per request), 1..256
     frames each, LLRs generated on the device with the library's encoder; they stay there
@@ -1140,9 +1155,11 @@ def run_serve(args):
     """Poisson arrivals of requests (1..256 frames of one code / D from the mixed
     distribution, LLRs resident on the device) at args.serve_load x the sustained frame
     rate of the mixed batch's persistent launch (measured here on an i.i.d. batch of the same
-    distribution), admitted by device-memory budget into 4 concurrent slots; reports request
-    latency percentiles and sustained payload bit/s."""
+    distribution), admitted by device-memory budget into 4 slots that share the GPU (a
+    quarter of the CUs each); reports request latency percentiles and sustained payload
+    bit/s."""
     import copy
+    import gc
 
     import torch
 
@@ -1182,14 +1199,14 @@ def run_serve(args):
     pool_frames = sum(r.frames for r in pool)
     log("serve: pool of %d device-resident requests (%d frames) ready" % (len(pool), pool_frames))
     be = GpuBackend(pcs, n_slots=4, max_frames=16384, host_inputs=False)
-    # saturated capacity of the server: the whole pool submitted at once, twice
-    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=16384)
+    # saturated capacity of the server: the whole pool submitted at once, six times
+    srv = Server(be, shapes, budget_bytes=SERVE_BUDGET, max_batch_frames=16384, keep_completed=False)
     t0 = time.perf_counter()
-    for rep_ in range(2):
+    for rep_ in range(6):
         for r in pool:
             srv.submit(copy.copy(r))
     srv.drain()
-    cap_fps = 2 * pool_frames / (time.perf_counter() - t0)
+    cap_fps = 6 * pool_frames / (time.perf_counter() - t0)
     log("serve: saturated server capacity %.0f frames/s" % cap_fps)
     # Poisson arrivals at the offered load for the run time
     rng = np.random.default_rng(6)
@@ -1203,10 +1220,21 @@ def run_serve(args):
         r.rid = k
         arrivals.append((t, r))
         k += 1
-    srv = Server(be, shapes, budget_bytes=1 << 30, max_batch_frames=16384)
+    srv = Server(be, shapes, budget_bytes=SERVE_BUDGET, max_batch_frames=16384, keep_completed=False)
     log("serve: replaying %d requests over %.0f s (%.0f frames/s offered)"
         % (len(arrivals), args.serve_seconds, offered_fps))
-    rep = srv.run(arrivals, progress=lambda msg: log("serve: " + msg))
+    # The million pre-generated requests would make every full collection of Python's cyclic
+    # garbage collector walk them all (pauses of a large fraction of a second, which queue
+    # up requests); the server makes no reference cycles, so the collector is parked for
+    # the run and the objects that exist now are frozen out of its view.
+    gc.collect()
+    gc.freeze()
+    gc.disable()
+    try:
+        rep = srv.run(arrivals, progress=lambda msg: log("serve: " + msg))
+    finally:
+        gc.enable()
+        gc.unfreeze()
     line = {
         "metric": "p50/p99 request latency and sustained info Mbit/s, continuous-batching server",
         "value": rep["payload_mbps"], "unit": "Mbit/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -1214,7 +1242,7 @@ def run_serve(args):
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded BPSK/AWGN requests of the mixed distribution, LLRs on the device",
         "config": {"workload": "serving: Poisson requests of 1-256 frames, mixed codes/D, "
-                               "4 slots, 1 GiB budget, device-resident LLRs",
+                               "4 slots sharing the GPU, 16 GiB budget, device-resident LLRs",
                    "offered_load": args.serve_load,
                    "mixed_batch_frames_per_s": c4_fps,
                    "offered_frames_per_s": offered_fps,
@@ -1224,6 +1252,8 @@ def run_serve(args):
                        "mean": rep["latency_ms_mean"]},
         "sustained_frames_per_s": rep["frames"] / rep["span_s"],
         "batches": rep["batches"], "max_concurrent_batches": be.max_concurrent,
+        "host_submit_ms_per_batch": rep["host_submit_ms_per_batch"],
+        "budget_bytes": rep["budget_bytes"], "peak_budget_bytes": rep["peak_budget_bytes"],
     }
     print(json.dumps(line))
 

@@ -127,6 +127,15 @@ void scs_ctx_destroy(scs_ctx* ctx);
  * than fit.  Results do not depend on this setting.  Errors: POLAR_EINVAL otherwise. */
 int scs_ctx_set_waves_per_block(scs_ctx* ctx, int32_t waves_per_block);
 
+/* Compute units' worth of workgroups a persistent mixed launch of this context takes (the
+ * grid is this many CUs times the workgroups one CU holds): 0 = every CU of the device (the
+ * default), else 1 .. the device's CU count.  Several contexts whose launches share the GPU
+ * (a server's slots, one stream each) can each take a part, so that one batch's last
+ * frames do not leave the rest of the GPU to wait for the next launch.  Results do not
+ * depend on this setting.  Errors: POLAR_EINVAL for a negative value or one above the
+ * device's CU count. */
+int scs_ctx_set_grid_cus(scs_ctx* ctx, int32_t cus);
+
 /* Per-frame counters (optional output of the decoders), one record per frame. */
 typedef struct {
   uint32_t iterations;  /* leaf estimates (path extensions) */

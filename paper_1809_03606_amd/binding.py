@@ -28,7 +28,8 @@ EXPORTS = ("polar_construct", "polar_construct_set", "polar_code_systematic",
            "polar_code_is_systematic", "polar_code_query", "polar_code_free", "polar_encode",
            "polar_encode_device", "scs_ctx_create", "scs_ctx_destroy", "scs_decode_batch",
            "scs_decode_mixed", "scs_mixed_prepare", "scs_mixed_launch",
-           "scs_decode_mixed_noalloc", "scs_ctx_set_waves_per_block", "scs_ctx_last_error", "polar_strerror",
+           "scs_decode_mixed_noalloc", "scs_ctx_set_waves_per_block", "scs_ctx_set_grid_cus",
+           "scs_ctx_last_error", "polar_strerror",
            "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch")
 
 STATS_FIELDS = ("iterations", "switches", "completions", "sc_elems", "fg_elems", "evictions",
@@ -95,6 +96,7 @@ def lib():
             L.scs_mixed_launch.argtypes = [vp, i32, vp, vp, vp, vp, vp]
             L.scs_ctx_last_error.argtypes = [vp]
             L.scs_ctx_set_waves_per_block.argtypes = [vp, i32]
+            L.scs_ctx_set_grid_cus.argtypes = [vp, i32]
             L.polar_code_schedule.argtypes = [vp, vp]
             L.fsscs_decode_batch.argtypes = [vp, vp, i32, i32, i32, vp, i64, vp, vp, vp, vp]
             L.scl_decode_batch.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, vp]
@@ -105,7 +107,8 @@ def lib():
                       "scs_ctx_create", "scs_decode_batch", "scs_decode_mixed",
                       "scs_decode_mixed_noalloc",
                       "scs_mixed_prepare", "scs_mixed_launch",
-                      "scs_ctx_set_waves_per_block", "scs_ctx_last_error",
+                      "scs_ctx_set_waves_per_block", "scs_ctx_set_grid_cus",
+                      "scs_ctx_last_error",
                       "polar_code_schedule", "fsscs_decode_batch", "scl_decode_batch"):
                 getattr(L, n).restype = ctypes.c_int
             _lib = L
@@ -351,6 +354,10 @@ def scs_ctx_set_waves_per_block(ctx: int, waves_per_block: int):
            "scs_ctx_set_waves_per_block")
 
 
+def scs_ctx_set_grid_cus(ctx: int, cus: int):
+    _check(lib().scs_ctx_set_grid_cus(ctx, int(cus)), "scs_ctx_set_grid_cus")
+
+
 def scs_ctx_last_error(ctx: int) -> int:
     return int(lib().scs_ctx_last_error(ctx))
 
@@ -434,6 +441,10 @@ class ScsContext:
 
     def configure(self, waves_per_block: int = 0):
         scs_ctx_set_waves_per_block(self.handle, waves_per_block)
+
+    def set_grid_cus(self, cus: int = 0):
+        """CUs' worth of workgroups of this context's persistent mixed launches (0: all)."""
+        scs_ctx_set_grid_cus(self.handle, cus)
 
     def _frames(self, code: PolarCode, llr_dev, payload_dev, status_dev, stats_dev):
         """Check the buffers of one batch; returns (LLR dtype code, frames)."""

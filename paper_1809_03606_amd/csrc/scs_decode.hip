@@ -557,6 +557,7 @@ struct scs_ctx {
   int wpb = 0;    // wavefronts per workgroup: 0 = automatic, else 1, 2 or 4
   int last_error = POLAR_OK;
   int cus = 0;    // compute units of the device
+  int grid_cus = 0;  // CUs' worth of workgroups of a persistent launch: 0 = cus
   std::mutex mu;
   // mixed-batch plan: device copies of the code tables, descriptors and the frame order,
   // the work counter, and a pinned staging area for the uploads
@@ -655,6 +656,13 @@ int scs_ctx_set_waves_per_block(scs_ctx* ctx, int32_t waves_per_block) {
     return POLAR_EINVAL;
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->wpb = waves_per_block;
+  return POLAR_OK;
+}
+
+int scs_ctx_set_grid_cus(scs_ctx* ctx, int32_t cus) {
+  if (!ctx || cus < 0 || cus > ctx->cus) return POLAR_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->grid_cus = cus;
   return POLAR_OK;
 }
 
@@ -816,14 +824,15 @@ int scs_mixed_prepare(scs_ctx* ctx, const polar_code* const* codes, int32_t n_co
   std::lock_guard<std::mutex> g(ctx->mu);
   if (hipSetDevice(ctx->device) != hipSuccess) return POLAR_EDEVICE;
   hipStream_t s = (hipStream_t)hip_stream;
-  // largest frames first, so that the work queue ends with short frames
+  // largest frames first (N L), so that the work queue ends with short frames
   std::vector<int32_t> order((size_t)n_frames);
-  for (int64_t f = 0; f < n_frames; ++f) order[f] = (int32_t)f;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    const int64_t wa = (int64_t)codes[frames_host[a].code]->N * frames_host[a].L;
-    const int64_t wb = (int64_t)codes[frames_host[b].code]->N * frames_host[b].L;
-    return wa > wb;
-  });
+  std::vector<int32_t> weight((size_t)n_frames);
+  for (int64_t f = 0; f < n_frames; ++f) {
+    order[f] = (int32_t)f;
+    weight[f] = codes[frames_host[f].code]->N * frames_host[f].L;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return weight[a] > weight[b]; });
   const size_t nc = (size_t)std::max(n_codes, 1), nf = (size_t)std::max<int64_t>(n_frames, 1);
   // grow-only device buffers (earlier launches may still read the old ones)
   if (nc > ctx->cap_codes || nf > ctx->cap_frames) {
@@ -900,7 +909,8 @@ int scs_mixed_launch(scs_ctx* ctx, int32_t llr_dtype, const void* llr_dev, uint8
       per_cu < 1)
     per_cu = 1;
   const int64_t need = ((int64_t)ctx->plan_frames + wpb - 1) / wpb;
-  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, need);
+  const int grid_cus = ctx->grid_cus ? ctx->grid_cus : ctx->cus;
+  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * grid_cus, need);
   // Launches of one context share its work counter: outside graph capture, a launch waits
   // for the context's previous one (on any stream) and is recorded for the next.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1013,7 +1023,8 @@ int scs_decode_mixed_noalloc(scs_ctx* ctx, const polar_code* const* codes, int32
       per_cu < 1)
     per_cu = 1;
   const int64_t want = (n_frames + wpb - 1) / wpb;
-  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * ctx->cus, want);
+  const int grid_cus = ctx->grid_cus ? ctx->grid_cus : ctx->cus;
+  const unsigned blocks = (unsigned)std::min<int64_t>((int64_t)per_cu * grid_cus, want);
   uint32_t* counter = (uint32_t*)base;
   const CodeArgs* d_codes = (const CodeArgs*)(base + off_codes);
   const scs_frame* d_frames = (const scs_frame*)(base + off_frames);

@@ -69,7 +69,12 @@ class GpuBackend:
     must have them written (and the writing stream synchronised) before submission."""
 
     def __init__(self, codes, n_slots: int = 4, max_frames: int = 4096, device: int = 0,
-                 host_inputs: bool = True):
+                 host_inputs: bool = True, share_gpu: bool = True):
+        """share_gpu: each slot's launches take 1 / n_slots of the CUs, so that the slots'
+        batches run side by side instead of one batch's last frames holding up the next.
+        Side by side needs a hardware queue per slot stream: HIP shares its queues
+        (GPU_MAX_HW_QUEUES, 4 by default) among all streams of the process, and launches in
+        one queue run one after another, so the process should allow n_slots + 2 or more."""
         import torch
 
         self.torch = torch
@@ -84,6 +89,8 @@ class GpuBackend:
         self.max_concurrent = 0  # most batches seen in flight at once
         self.slots = []
         stage = max_frames * maxN if host_inputs else 0
+        cus = torch.cuda.get_device_properties(self.dev).multi_processor_count
+        share = max(1, cus // n_slots) if share_gpu and n_slots > 1 else 0
         for _ in range(n_slots):
             s = {
                 "stream": torch.cuda.Stream(device=self.dev),
@@ -96,6 +103,8 @@ class GpuBackend:
                 "h_st": torch.empty(max_frames, dtype=torch.uint8, pin_memory=True),
                 "event": None, "batch": None, "busy": False,
             }
+            if share:
+                s["ctx"].set_grid_cus(share)
             # size the context's plan buffers once, so that no submission has to grow them
             big = max(range(len(codes)), key=lambda c: codes[c].N)
             plan = np.zeros(max_frames, binding.FRAME_DTYPE)
@@ -154,11 +163,12 @@ class GpuBackend:
         with torch.cuda.stream(st):
             binding.scs_decode_mixed(s["ctx"].handle, self.handles, frames, binding.SCS_LLR_F32,
                                      llr_arg, s["d_pay"], s["d_st"], None, st)
-            s["h_pay"][:lo_o].copy_(s["d_pay"][:lo_o], non_blocking=True)
-            s["h_st"][:n].copy_(s["d_st"][:n], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        s.update(event=ev, batch=(reqs, spans), busy=True)
+        # The results are copied back in collect(), once the batch is done: an asynchronous
+        # device-to-host copy enqueued here was measured to hold back the other slots'
+        # launches until this batch had finished, serialising the slots.
+        s.update(event=ev, batch=(reqs, spans, lo_o, n), busy=True)
         self.max_concurrent = max(self.max_concurrent, sum(x["busy"] for x in self.slots))
 
     def done(self, slot: int) -> bool:
@@ -167,7 +177,10 @@ class GpuBackend:
 
     def collect(self, slot: int):
         s = self.slots[slot]
-        reqs, spans = s["batch"]
+        reqs, spans, lo_o, n = s["batch"]
+        with self.torch.cuda.stream(s["stream"]):  # the batch is done: these return at once
+            s["h_pay"][:lo_o].copy_(s["d_pay"][:lo_o])
+            s["h_st"][:n].copy_(s["d_st"][:n])
         hp, hs = s["h_pay"].numpy(), s["h_st"].numpy()
         for r, (f, lo_o, m, kp) in zip(reqs, spans):
             r.payload = hp[lo_o:lo_o + m * kp].reshape(m, kp).copy()
@@ -180,17 +193,30 @@ class Server:
     """FIFO admission under a device-memory budget, continuous batching over the slots."""
 
     def __init__(self, backend, code_shapes, budget_bytes: int = 512 << 20,
-                 max_batch_frames: int = 4096, clock=time.perf_counter):
+                 max_batch_frames: int = 4096, clock=time.perf_counter,
+                 keep_completed: bool = True, on_complete=None):
+        """keep_completed: finished requests are appended to `completed` (a long-running
+        server passes False and takes them through `on_complete(request)` instead, so that
+        it holds nothing per finished request beyond its latency)."""
         self.backend = backend
         self.shapes = code_shapes  # list of (N, kp)
         self.budget = int(budget_bytes)
         self.max_batch_frames = int(max_batch_frames)
         self.clock = clock
+        self.keep_completed = keep_completed
+        self.on_complete = on_complete
         self.waiting = collections.deque()
         self.in_use = 0
         self.peak_in_use = 0
         self.completed = []
         self.batches = 0
+        # running totals of the finished requests, for report()
+        self.latencies = []  # seconds, arrival to completion
+        self.done_frames = 0
+        self.done_bits = 0
+        self.t_first = float("inf")
+        self.t_last = float("-inf")
+        self.submit_s = 0.0  # host time spent handing batches to the backend
 
     def footprint(self, r: Request) -> int:
         N, kp = self.shapes[r.code]
@@ -222,7 +248,15 @@ class Server:
                 for r in self.backend.collect(slot):
                     r.t_done = now
                     self.in_use -= r.footprint
-                    self.completed.append(r)
+                    self.latencies.append(now - r.t_arrival)
+                    self.done_frames += r.frames
+                    self.done_bits += r.frames * self.shapes[r.code][1]
+                    self.t_first = min(self.t_first, r.t_arrival)
+                    self.t_last = max(self.t_last, now)
+                    if self.keep_completed:
+                        self.completed.append(r)
+                    if self.on_complete is not None:
+                        self.on_complete(r)
                     finished += 1
         for slot in self.backend.free_slots():
             if not self.waiting:
@@ -243,7 +277,9 @@ class Server:
                 r.t_admit = now
             self.in_use += need
             self.peak_in_use = max(self.peak_in_use, self.in_use)
+            t_sub = time.perf_counter()
             self.backend.submit(slot, batch)
+            self.submit_s += time.perf_counter() - t_sub
             self.batches += 1
         return finished
 
@@ -279,17 +315,15 @@ class Server:
         return self.report()
 
     def report(self):
-        lat = np.array([r.t_done - r.t_arrival for r in self.completed])
+        lat = np.asarray(self.latencies)
         if lat.size == 0:
             return {"requests": 0}
-        t_first = min(r.t_arrival for r in self.completed)
-        t_last = max(r.t_done for r in self.completed)
-        bits = sum(r.frames * self.shapes[r.code][1] for r in self.completed)
-        frames = sum(r.frames for r in self.completed)
-        return {"requests": len(self.completed), "frames": frames, "batches": self.batches,
+        span = self.t_last - self.t_first
+        return {"requests": int(lat.size), "frames": self.done_frames, "batches": self.batches,
                 "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
                 "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
                 "latency_ms_mean": float(lat.mean() * 1e3),
-                "payload_mbps": bits / max(t_last - t_first, 1e-9) / 1e6,
-                "span_s": t_last - t_first, "peak_budget_bytes": self.peak_in_use,
-                "budget_bytes": self.budget}
+                "payload_mbps": self.done_bits / max(span, 1e-9) / 1e6,
+                "span_s": span, "peak_budget_bytes": self.peak_in_use,
+                "budget_bytes": self.budget,
+                "host_submit_ms_per_batch": 1e3 * self.submit_s / max(self.batches, 1)}

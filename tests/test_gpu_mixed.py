@@ -201,6 +201,31 @@ def test_gpu_mixed_every_workgroup_size_matches_oracle(cuda, wpb):
         assert (pay[o:o + kp] == want[f][0]).all() and st[f] == want[f][1], (wpb, f)
 
 
+@pytest.mark.parametrize("grid_cus", [1, 37, 0])
+def test_gpu_mixed_grid_share_matches_oracle(cuda, grid_cus):
+    """A persistent launch confined to a part of the CUs (scs_ctx_set_grid_cus, as the
+    serving slots use it) gives the oracle's bits; out-of-range settings are refused."""
+    from paper_1809_03606_amd import binding
+    from paper_1809_03606_amd.binding import PolarCode, PolarError
+
+    B = 400
+    codes, frames, flat, per, want, total_out = build_mixed(B, seed=70 + grid_cus)
+    pcs = [PolarCode(N, K, 16, 2.0) for (N, K) in codes]
+    ctx = binding.ScsContext(0)
+    cus = cuda.cuda.get_device_properties(0).multi_processor_count
+    for bad in (-1, cus + 1):
+        with pytest.raises(PolarError):
+            ctx.set_grid_cus(bad)
+    ctx.set_grid_cus(grid_cus)
+    _say("gpu: mixed batch on %d CUs' worth of workgroups" % grid_cus)
+    pay, st, stats = _gpu_mixed(cuda, [p.handle for p in pcs], frames, flat, total_out, ctx=ctx)
+    for f in range(B):
+        c = frames["code"][f]
+        kp = codes[c][1] - 16
+        o = frames["out_off"][f]
+        assert (pay[o:o + kp] == want[f][0]).all() and st[f] == want[f][1], (grid_cus, f)
+
+
 def test_gpu_mixed_plan_tuner(cuda, tmp_path):
     """tune_mixed times the persistent launch at every workgroup size on the caller's plan,
     checks the bytes agree, stores the fastest under the plan's key and applies it."""

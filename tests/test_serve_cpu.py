@@ -78,3 +78,25 @@ def test_over_budget_request_is_rejected_and_cancel_works():
     assert srv2.cancel(reqs[2].rid) and not srv2.cancel(999)
     srv2.drain()
     assert sorted(r.rid for r in srv2.completed) == [reqs[0].rid, reqs[1].rid]
+
+
+def test_long_running_server_keeps_totals_not_requests():
+    """keep_completed=False: finished requests go to the callback only; the report comes from
+    running totals and equals the one a keeping server gives on the same requests."""
+    infos, reqs = make_requests(25, seed=6)
+    shapes = [(N, K - CRC) for N, K in CODES]
+    got = []
+    reps = []
+    for keep in (True, False):
+        be = OracleBackend(infos, CRC, n_slots=2)
+        srv = Server(be, shapes, budget_bytes=10 ** 9, max_batch_frames=16, clock=FakeClock(),
+                     keep_completed=keep, on_complete=None if keep else got.append)
+        for r in reqs:
+            srv.submit(r)
+        srv.drain()
+        assert len(srv.completed) == (25 if keep else 0)
+        reps.append(srv.report())
+    assert sorted(r.rid for r in got) == list(range(25))
+    a, b = reps
+    assert a["requests"] == b["requests"] == 25 and a["frames"] == b["frames"] == sum(r.frames for r in reqs)
+    assert b["payload_mbps"] > 0 and b["latency_ms_p99"] >= b["latency_ms_p50"] > 0
