@@ -976,8 +976,13 @@ def run_fixed(args):
     out = torch.empty((B, kp), dtype=torch.uint8, device=dev)
     st = torch.empty((B,), dtype=torch.uint8, device=dev)
 
+    from paper_1809_03606_amd import tune
+
     def decode(x, n):
         dt = binding.SCS_LLR_F32 if x.dtype == torch.float32 else binding.SCS_LLR_I8
+        # each precision at its tuned workgroup size (the library default when none is stored)
+        ctx.configure(0)
+        tune.apply(ctx, code, D, L, "f32" if dt == binding.SCS_LLR_F32 else "i8")
         # x was just written on the default stream: the decoder's stream waits for it
         stream.wait_stream(torch.cuda.current_stream())
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
