@@ -131,10 +131,14 @@ struct TrF32 {
   __device__ static __forceinline__ uint32_t load(const float* p, int64_t j) {
     return __float_as_uint(p[j]);
   }
-  // f = sign(a) sign(b) min(|a|, |b|), sign from the IEEE sign bits.
+  // f = sign(a) sign(b) min(|a|, |b|), sign from the IEEE sign bits.  The minimum of the
+  // magnitudes is one v_min_f32 with absolute-value modifiers: the same value fminf gives for
+  // every non-NaN input, without the two canonicalising instructions the compiler puts in
+  // front of fminf for operands it cannot prove canonical (they arrive here as bit patterns).
   __device__ static __forceinline__ uint32_t f(uint32_t a, uint32_t b) {
-    const float m = fminf(fabsf(__uint_as_float(a)), fabsf(__uint_as_float(b)));
-    return __float_as_uint(m) | ((a ^ b) & 0x80000000u);
+    uint32_t m;
+    asm("v_min_f32_e64 %0, |%1|, |%2|" : "=v"(m) : "v"(a), "v"(b));
+    return m | ((a ^ b) & 0x80000000u);
   }
   // g = b + (-1)^u a, one binary32 addition.
   __device__ static __forceinline__ uint32_t g(uint32_t a, uint32_t b, bool u) {
@@ -154,10 +158,13 @@ struct TrI8 {
     const int v = p[j];
     return (uint32_t)(v < -127 ? -127 : v);
   }
+  // f = sign(a) sign(b) min(|a|, |b|) (0 when either is 0), computed as
+  // max(min(a, b), -max(a, b)), four instructions instead of nine: both >= 0 gives min(a, b);
+  // both <= 0 gives -max(a, b) = min(|a|, |b|); a < 0 < b gives max(a, -b) = -min(|a|, b)
+  // (and symmetrically); no overflow for the int8 range these values stay in.
   __device__ static __forceinline__ uint32_t f(uint32_t a, uint32_t b) {
     const int ia = (int)a, ib = (int)b;
-    const int m = min(abs(ia), abs(ib));
-    return (uint32_t)(((ia ^ ib) < 0) ? -m : m);
+    return (uint32_t)max(min(ia, ib), -max(ia, ib));
   }
   __device__ static __forceinline__ uint32_t g(uint32_t a, uint32_t b, bool u) {
     const int s = (int)b + (u ? -(int)a : (int)a);
