@@ -38,15 +38,17 @@ def sweep_config(d, l):
 POINTS = (1.0, 1.5, 2.0, 2.5, 3.0)
 SEED = 2
 PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 32-bit VALU lane-operations per second
-# Algorithmic lane-operations (see the design notes): 3 per f/g element of the SC
-# schedule, and per path extension 4 D for the best/worst-path searches over the stack
-# plus 8 for the leaf decision, metric, CRC register and counters.
+# Algorithmic lane-operations, the cost model the measurement plan fixes: f = 4 and g = 2
+# operations per value (3 on average over the SC schedule, which evaluates as many f as g
+# values), and per path extension 2 for the hard decision and the path metric and 8 for the
+# stack (6 DPP steps and 2 ballots of one best-path search).  Earlier versions charged the
+# stack 4 D per extension (both searches over every slot), which overstated the work.
 OPS_PER_ELEM = 3
-OPS_PER_ITER_FIXED = 8
+OPS_PER_ITER_FIXED = 10
 
 
 def ops_per_iteration(d: int) -> int:
-    return 4 * d + OPS_PER_ITER_FIXED
+    return OPS_PER_ITER_FIXED
 
 
 def log(msg):
@@ -624,7 +626,7 @@ def main():
         s = stats.cpu().numpy().view(np.uint32).astype(np.int64)
         it, sc = s[:, 0].sum(), s[:, 3].sum()
         if scl:  # every list entry runs the SC schedule: N log2 N f/g values per entry
-            work_ops[eb] = OPS_PER_ELEM * (it / N) * N * int(np.log2(N)) + 8 * it
+            work_ops[eb] = OPS_PER_ELEM * (it / N) * N * int(np.log2(N)) + OPS_PER_ITER_FIXED * it
         else:
             work_ops[eb] = OPS_PER_ELEM * sc + ops_per_iteration(D) * it
         fer = float((out_pay != pay).any(dim=1).float().mean().item())
