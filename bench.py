@@ -428,6 +428,64 @@ def write_traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, frames=1_
     print(json.dumps({"traffic_record": path, "hbm_bytes_per_frame": rec["hbm_bytes_per_frame"]}))
 
 
+def write_workload_trace_summary(trace_dir, bench_json, out_md):
+    """Markdown summary of a kernel trace of `python bench.py --workload mixed|serve`: the
+    kernels by GPU time, and for the persistent mixed launches their number, durations and
+    how many ran at once on average (the sum of their durations over the span they cover)."""
+    rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    serve = "latency_ms" in b
+    per, mixed = {}, []
+    for r in rows:
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        short = name.split("(")[0].strip()[:90]
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        per.setdefault(short, []).append((t1 - t0) * 1e-6)
+        if short.startswith("scs_mixed_kernel"):
+            mixed.append((t0, t1))
+    total = sum(sum(v) for v in per.values())
+    cmd = "--workload serve" if serve else "--workload mixed"
+    lines = ["# Kernel trace: %s workload" % ("serving" if serve else "mixed-batch"), "",
+             "Command (from the repository root on one MI355X):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
+             "python bench.py %s" % cmd, "",
+             "Workload: %s.  Bench line of the same run: %.1f Mbit/s%s." % (
+                 b["config"]["workload"], b["value"],
+                 (", %.0f frames/s offered, %.0f sustained, request latency p50 %.1f ms, p99 %.1f ms"
+                  % (b["config"]["offered_frames_per_s"], b["sustained_frames_per_s"],
+                     b["latency_ms"]["p50"], b["latency_ms"]["p99"])) if serve else
+                 (", %.0f frames/s, %.2fx the one-launch-per-configuration form"
+                  % (b["frames_per_s"], b["mixed_over_plain"]))), "",
+             "| kernel | calls | average ms | min ms | max ms | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:8]:
+        lines.append("| %s | %d | %.3f | %.3f | %.3f | %.2f%% |" % (
+            k, len(v), np.mean(v), min(v), max(v), 100.0 * sum(v) / total))
+    if serve and mixed:
+        # the serving phase is the run's last: keep the launches of its span only
+        t_end = max(t1 for _, t1 in mixed)
+        mixed = [(t0, t1) for t0, t1 in mixed if t0 >= t_end - b["ms_per_step"] * 1e6]
+    if mixed:
+        mixed.sort()
+        busy = sum(t1 - t0 for t0, t1 in mixed)
+        span, cur0, cur1 = 0, mixed[0][0], mixed[0][1]
+        for t0, t1 in mixed[1:]:
+            if t0 > cur1:
+                span += cur1 - cur0
+                cur0, cur1 = t0, t1
+            else:
+                cur1 = max(cur1, t1)
+        span += cur1 - cur0
+        lines += ["", "Persistent mixed launches%s: %d, mean %.3f ms; on average %.2f of them "
+                  "ran at once over the %.1f s they cover." % (
+                      " of the serving span" if serve else "", len(mixed),
+                      busy * 1e-6 / len(mixed), busy / max(span, 1), span * 1e-9)]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def write_trace_summary(trace_dir, bench_json, out_md):
     """Markdown summary of a kernel trace of `python bench.py --cpu-sample 0
     --latency-requests 0`: per-kernel statistics, and the decoder's mean duration beside
@@ -515,7 +573,12 @@ def main():
         write_counters_record(*args.counters_record)
         return
     if args.trace_summary:
-        write_trace_summary(*args.trace_summary)
+        with open(args.trace_summary[1]) as fh:
+            line = [ln for ln in fh.read().splitlines() if ln.startswith("{")][-1]
+        if "roofline" in json.loads(line):
+            write_trace_summary(*args.trace_summary)
+        else:
+            write_workload_trace_summary(*args.trace_summary)
         return
     if args.workload == "serve":
         # The serving slots run their batches side by side only from separate hardware queues:

@@ -145,3 +145,32 @@ def test_util_record_and_rocprof_figures(sources, tmp_path, monkeypatch):
     assert got["lds_frac_measured"] == pytest.approx(1600.0 * ext_per_s / 1e12)
     sources.write_text("int f() {\n  return 4;\n}\n")
     assert bench.rocprof_use({2.0: {"mean_iterations": 100.0, "launch_ms": 2.0}}, 1000) is None
+
+
+def _trace(folder, rows):
+    os.makedirs(folder, exist_ok=True)
+    with open(os.path.join(folder, "run_kernel_trace.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, t0, t1 in rows:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": t0, "End_Timestamp": t1})
+
+
+def test_serve_trace_summary_counts_overlap_in_the_serving_span(tmp_path):
+    ms = 1_000_000
+    mk = "void scs_mixed_kernel<(anonymous namespace)::TrF32>(int)"
+    # one launch long before the serving span (capacity probe), then two overlapping pairs
+    _trace(str(tmp_path / "t"), [(mk, 0, 10 * ms), ("fill_kernel(int)", 20 * ms, 21 * ms),
+                                 (mk, 1000 * ms, 1010 * ms), (mk, 1000 * ms, 1010 * ms),
+                                 (mk, 1020 * ms, 1030 * ms), (mk, 1025 * ms, 1035 * ms)])
+    line = {"value": 900.0, "ms_per_step": 40.0, "config": {"workload": "serving",
+            "offered_frames_per_s": 1e6}, "sustained_frames_per_s": 1e6,
+            "latency_ms": {"p50": 20.0, "p99": 30.0}}
+    (tmp_path / "b.json").write_text("log line\n" + json.dumps(line) + "\n")
+    out = tmp_path / "s.md"
+    bench.write_workload_trace_summary(str(tmp_path / "t"), str(tmp_path / "b.json"), str(out))
+    text = out.read_text()
+    # serving span: 4 launches, 40 ms busy over 25 ms covered
+    assert "launches of the serving span: 4, mean 10.000 ms" in text
+    assert "1.60 of them ran at once" in text
+    assert "--workload serve" in text and "| scs_mixed_kernel<TrF32> | 5 |" in text
