@@ -88,6 +88,9 @@ def parse():
                          "serve: Poisson requests through the continuous-batching server")
     ap.add_argument("--latency-requests", type=int, default=300,
                     help="closed-loop requests timed for the latency percentiles of the sweep")
+    ap.add_argument("--e2e-reps", type=int, default=None,
+                    help="repetitions of the end-to-end run from pinned host memory (0: off; "
+                         "default 3, or 0 with --latency-requests 0, as the profile records run)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the mixed batch's sustained frame rate "
@@ -747,6 +750,57 @@ def main():
         req_ms.append((time.perf_counter() - t0) * 1e3)
     req_ms = np.array(req_ms) if req_ms else np.zeros(1)
 
+    # -- end to end from host memory (untimed for `value`): the point's LLRs in pinned host
+    # memory are copied in, decoded and their payload and status copied back, in eight chunks
+    # alternating over two streams so that one chunk's copies overlap another's decoding --
+    e2e = None
+    e2e_reps = args.e2e_reps if args.e2e_reps is not None else (3 if args.latency_requests else 0)
+    if e2e_reps > 0:
+        h_llr = torch.empty(lat_llr.shape, dtype=lat_llr.dtype, pin_memory=True)
+        h_llr.copy_(lat_llr)
+        h_pay = torch.empty((B, kp), dtype=torch.uint8, pin_memory=True)
+        h_st = torch.empty((B,), dtype=torch.uint8, pin_memory=True)
+        d_llr = torch.empty_like(lat_llr)
+        launch(lat_llr)
+        stream.synchronize()
+        ref_pay, ref_st = out_pay.cpu(), out_st.cpu()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):  # the host-to-device copy alone
+            a.record(stream)
+            d_llr.copy_(h_llr, non_blocking=True)
+            b.record(stream)
+        stream.synchronize()
+        h2d_ms = a.elapsed_time(b)
+        streams = [stream, torch.cuda.Stream(device=dev)]
+        chunk = (B + 7) // 8
+        e2e_ms = []
+        for _ in range(e2e_reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c, lo in enumerate(range(0, B, chunk)):
+                hi = min(B, lo + chunk)
+                s = streams[c % 2]
+                with torch.cuda.stream(s):
+                    d_llr[lo:hi].copy_(h_llr[lo:hi], non_blocking=True)
+                    decode_fn(ctx.handle, code.handle, D, L, llr_dtype, d_llr[lo:hi], hi - lo,
+                              out_pay[lo:hi], out_st[lo:hi], None, s)
+                    h_pay[lo:hi].copy_(out_pay[lo:hi], non_blocking=True)
+                    h_st[lo:hi].copy_(out_st[lo:hi], non_blocking=True)
+            for s in streams:
+                s.synchronize()
+            e2e_ms.append((time.perf_counter() - t0) * 1e3)
+        ms_e = float(np.mean(e2e_ms))
+        e2e = {"ebn0_db": lat_eb, "frames": B, "chunks": (B + chunk - 1) // chunk, "streams": 2,
+               "ms": ms_e, "payload_mbps": B * kp / (ms_e * 1e-3) / 1e6,
+               "h2d_bytes": h_llr.numel() * h_llr.element_size(), "h2d_ms": h2d_ms,
+               "h2d_gbps": h_llr.numel() * h_llr.element_size() / (h2d_ms * 1e-3) / 1e9,
+               "equals_device_resident": bool(torch.equal(h_pay, ref_pay) and
+                                              torch.equal(h_st, ref_st)),
+               "note": "LLRs from pinned host memory and results back to it, host clock, "
+                       "mean of %d runs; not the bench value" % e2e_reps}
+        log("end to end from host memory: %.1f ms, %.0f Mbit/s" % (ms_e, e2e["payload_mbps"]))
+        del h_llr, h_pay, h_st, d_llr, ref_pay, ref_st
+
     launch_ms = {eb: [] for eb in points}
     for eb, a, b in ev:
         launch_ms[eb].append(a.elapsed_time(b))
@@ -837,6 +891,8 @@ def main():
                     "batch_launch_ms_p50": float(np.percentile(all_ms, 50)),
                     "batch_launch_ms_p99": float(np.percentile(all_ms, 99))},
         "per_point": {str(k): v for k, v in per_point.items()},
+        "k_bit_mbps": value * K / kp,
+        "end_to_end_from_host": e2e,
         "wall_s": wall, "input_generation_s": gen_s,
         "roofline": roofline,
         "cpu_baseline": cpu,
