@@ -4,8 +4,8 @@ Requests (one code, one D and L, 1..256 frames each) arrive over time.  The serv
 FIFO of waiting requests and several device slots (one HIP stream and one decoder context
 each).  Whenever a slot is free it admits waiting requests, oldest first, while their
 device footprint fits the free part of the memory budget, and enqueues one mixed-batch
-decode (``scs_decode_mixed``) of all their frames plus the copy of the results back; batches
-of different slots run concurrently on the GPU.  A request's LLRs are either in host memory
+decode (``scs_decode_mixed``) of all their frames; the results are copied back once the
+batch is done.  Batches of different slots run concurrently on the GPU.  A request's LLRs are either in host memory
 (packed into the slot's pinned staging buffer and copied to the device with the batch) or
 already on the device (a CUDA tensor, for example written there by a demodulator): then the
 batch's descriptors point at them where they are and nothing is copied in.  A request that arrives while others are decoding joins the next
@@ -308,7 +308,7 @@ class Server:
                 k += 1
             if progress is not None and now >= next_report:
                 progress("%.0f s: %d arrived, %d completed, %d waiting, %d batches"
-                         % (now, k, len(self.completed), len(self.waiting), self.batches))
+                         % (now, k, len(self.latencies), len(self.waiting), self.batches))
                 next_report += every_s
             if self.step() == 0:
                 time.sleep(poll_s)

@@ -100,3 +100,17 @@ def test_long_running_server_keeps_totals_not_requests():
     a, b = reps
     assert a["requests"] == b["requests"] == 25 and a["frames"] == b["frames"] == sum(r.frames for r in reqs)
     assert b["payload_mbps"] > 0 and b["latency_ms_p99"] >= b["latency_ms_p50"] > 0
+
+
+def test_progress_counts_completions_without_keeping_them():
+    """The progress line of run() counts finished requests from the running totals, so a
+    long-running server (keep_completed=False) reports them too."""
+    infos, reqs = make_requests(12, seed=8)
+    shapes = [(N, K - CRC) for N, K in CODES]
+    be = OracleBackend(infos, CRC, n_slots=2)
+    srv = Server(be, shapes, budget_bytes=10 ** 9, max_batch_frames=16, clock=FakeClock(),
+                 keep_completed=False, on_complete=lambda r: None)
+    msgs = []
+    srv.run([(0.0, r) for r in reqs], poll_s=0.0, progress=msgs.append, every_s=2e-4)
+    done = [int(m.split(" arrived, ")[1].split(" completed")[0]) for m in msgs]
+    assert done and max(done) > 0 and srv.report()["requests"] == 12
