@@ -54,7 +54,12 @@ def _full(cuda, ebn0, dtype, seed, decoder="scs", list_size=L):
     out = torch.empty((FRAMES, kp), dtype=torch.uint8, device="cuda")
     st = torch.empty((FRAMES,), dtype=torch.uint8, device="cuda")
     ctx = binding.ScsContext(0)
-    _say("gpu: full-size %s %s batch at %.1f dB (list %d)" % (decoder, dtype, ebn0, list_size))
+    # the workgroup size the benchmark applies: the tuner's stored choice, else the library's
+    from paper_1809_03606_amd import tune
+
+    entry = tune.apply(ctx, code, D, list_size, dtype, decoder=decoder)
+    _say("gpu: full-size %s %s batch at %.1f dB (list %d), %s wavefronts per workgroup"
+         % (decoder, dtype, ebn0, list_size, entry["waves_per_block"] if entry else "default"))
     if decoder == "scl":
         ctx.decode_list(code, list_size, llr, out, st)
     else:
