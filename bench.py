@@ -38,6 +38,16 @@ def sweep_config(d, l):
 POINTS = (1.0, 1.5, 2.0, 2.5, 3.0)
 SEED = 2
 PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 32-bit VALU lane-operations per second
+
+# The paper's own throughput at Eb/N0 = POINTS (Section 5, throughput figure), Mbit/s of
+# information bits per thread of a six-thread AMD Ryzen 5 1600 at 3.2 GHz, for PC(1024,512)
+# with the 5G information set, CRC-24C, L = 8 and D = 8192: context only (another machine,
+# code set, CRC and stack depth).
+PAPER_TP_MBPS = {
+    "scs": ("SCS-RM", (0.0346253, 0.0518958, 0.0721866, 0.110722, 0.232370)),
+    "fsscs": ("FSSCS-RM", (0.232408, 0.342818, 0.448689, 0.619550, 0.925226)),
+    "scl": ("SCL", (0.290247, 0.280185, 0.290871, 0.309693, 0.314545)),
+}
 # Algorithmic lane-operations, the cost model the measurement plan fixes: f = 4 and g = 2
 # operations per value (3 on average over the SC schedule, which evaluates as many f as g
 # values), and per path extension 2 for the hard decision and the path metric and 8 for the
@@ -892,12 +902,24 @@ def main():
                     "batch_launch_ms_p99": float(np.percentile(all_ms, 99))},
         "per_point": {str(k): v for k, v in per_point.items()},
         "k_bit_mbps": value * K / kp,
+        "paper_context": paper_context(args.decoder),
         "end_to_end_from_host": e2e,
         "wall_s": wall, "input_generation_s": gen_s,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def paper_context(decoder: str):
+    """The paper's per-thread CPU throughput for the same decoder, with its setup."""
+    if decoder not in PAPER_TP_MBPS:
+        return None
+    name, tp = PAPER_TP_MBPS[decoder]
+    return {"decoder": name, "mbps_per_thread": {str(e): v for e, v in zip(POINTS, tp)},
+            "hardware": "AMD Ryzen 5 1600 at 3.2 GHz, 6 threads, average per thread",
+            "workload": "PC(1024,512), 5G information set, CRC-24C, L=8, D=8192",
+            "note": "the paper's figures on its own machine and code; context, not vs_baseline"}
 
 
 def mixed_batch(torch, dev, B, seed, pcs, codes, stream, Lp=8, crc=16):

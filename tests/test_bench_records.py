@@ -174,3 +174,11 @@ def test_serve_trace_summary_counts_overlap_in_the_serving_span(tmp_path):
     assert "launches of the serving span: 4, mean 10.000 ms" in text
     assert "1.60 of them ran at once" in text
     assert "--workload serve" in text and "| scs_mixed_kernel<TrF32> | 5 |" in text
+
+
+def test_paper_context_matches_the_decoder():
+    c = bench.paper_context("scs")
+    assert c["decoder"] == "SCS-RM" and c["mbps_per_thread"]["3.0"] == pytest.approx(0.23237)
+    assert bench.paper_context("fsscs")["mbps_per_thread"]["3.0"] == pytest.approx(0.925226)
+    assert bench.paper_context("fssc") is None
+    assert all(len(v[1]) == len(bench.POINTS) for v in bench.PAPER_TP_MBPS.values())
