@@ -66,12 +66,9 @@ __device__ __forceinline__ uint32_t sibling_big(uint32_t u, int base, int lane) 
   return x;
 }
 
-// Bit e = 64 r + lane of a lane-per-word partial-sum vector bx (sibling_big) whose block
-// starts at word w0 (the vector's bits 32 w0 + 64 r .. + 63 belong to chunk r).
-__device__ __forceinline__ bool chunk_bit(uint32_t bx, int w0, int r, int lane) {
-  const uint32_t mlo = readlane(bx, w0 + 2 * r), mhi = readlane(bx, w0 + 2 * r + 1);
-  const uint32_t m = lane < 32 ? mlo : mhi;
-  return (m >> (lane & 31)) & 1u;
+// Word w of a lane-per-word vector, in every lane (w may differ between lanes).
+__device__ __forceinline__ uint32_t lane_word(uint32_t x, int w) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(w << 2, (int)x);
 }
 
 // Stage n-2 of a code whose stage n-1 is not kept (Layout::KEEP_TOP false): value e of
@@ -91,21 +88,39 @@ __device__ __forceinline__ void top_two_stages(int i, uint32_t u,
   if (odd1) b1 = sibling_big<L1>(u, 0, lane);      // partial sums of bits [0, N/2)
   if (odd2) b2 = sibling_big<L2>(u, base2, lane);
   uint32_t* dst = al + (Lam2 - 1);
-#pragma unroll
-  for (int r = 0; r < Lam2 / kWave; ++r) {
-    const int e = r * kWave + lane;
-    const uint32_t a0 = TR::load(root, e), a1 = TR::load(root, e + Lam1);
-    const uint32_t c0 = TR::load(root, e + Lam2), c1 = TR::load(root, e + Lam2 + Lam1);
-    uint32_t p0, p1;
-    if (odd1) {
-      p0 = TR::g(a0, a1, chunk_bit(b1, 0, r, lane));
-      p1 = TR::g(c0, c1, chunk_bit(b1, 0, r + Lam2 / kWave, lane));
-    } else {
-      p0 = TR::f(a0, a1);
-      p1 = TR::f(c0, c1);
-    }
-    dst[e] = odd2 ? TR::g(p0, p1, chunk_bit(b2, base2 >> 5, r, lane)) : TR::f(p0, p1);
+  // Lane l makes values e = V l .. V l + V - 1: each operand is V consecutive channel LLRs,
+  // and the partial-sum bits of those values sit in one word (V divides 32).
+  constexpr int V = Lam2 / kWave;
+  static_assert(V <= 32 && 32 % V == 0, "a lane's values share one partial-sum word");
+  const int e0 = V * lane;
+  uint32_t m1 = 0u, m1c = 0u, m2 = 0u;
+  if (odd1) {
+    m1 = lane_word(b1, e0 >> 5) >> (e0 & 31);
+    m1c = lane_word(b1, (e0 + Lam2) >> 5) >> (e0 & 31);
   }
+  if (odd2) m2 = lane_word(b2, (base2 >> 5) + (e0 >> 5)) >> (e0 & 31);
+  uint32_t p0[V], p1[V];
+  {
+    uint32_t x[V], y[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) x[k] = TR::load(root, e0 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) y[k] = TR::load(root, e0 + Lam1 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) p0[k] = odd1 ? TR::g(x[k], y[k], (m1 >> k) & 1u) : TR::f(x[k], y[k]);
+  }
+  {
+    uint32_t x[V], y[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) x[k] = TR::load(root, e0 + Lam2 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) y[k] = TR::load(root, e0 + Lam2 + Lam1 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) p1[k] = odd1 ? TR::g(x[k], y[k], (m1c >> k) & 1u) : TR::f(x[k], y[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+    dst[e0 + k] = odd2 ? TR::g(p0[k], p1[k], (m2 >> k) & 1u) : TR::f(p0[k], p1[k]);
   if constexpr (STATS) fg += (uint32_t)(Lam1 + Lam2);
   lds_order();
 }
