@@ -63,14 +63,25 @@ __device__ __forceinline__ void big_stages_to(int top, int bottom, int i, uint32
       if (odd) bx = sibling_big<LAM>(u, base, lane);
       uint32_t* dst = al + (Lam - 1);
       const uint32_t* src = al + (2 * Lam - 1);
-      if (!odd) {
+      if constexpr (LAM + 1 == LOGN) {
+        // from the channel LLRs: lane l makes the V consecutive values V l .. V l + V - 1,
+        // so each operand is V consecutive LLRs and their partial-sum bits one word
+        constexpr int V = Lam / kWave;
+        const int e0 = V * lane;
+        const uint32_t m = odd ? lane_word(bx, (base >> 5) + (e0 >> 5)) >> (e0 & 31) : 0u;
+        uint32_t x[V], y[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) x[k] = TR::load(root, e0 + k);
+#pragma unroll
+        for (int k = 0; k < V; ++k) y[k] = TR::load(root, e0 + Lam + k);
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+          dst[e0 + k] = odd ? TR::g(x[k], y[k], (m >> k) & 1u) : TR::f(x[k], y[k]);
+      } else if (!odd) {
 #pragma unroll
         for (int r = 0; r < Lam / kWave; ++r) {
           const int e = r * kWave + lane;
-          if constexpr (LAM + 1 == LOGN)
-            dst[e] = TR::f(TR::load(root, e), TR::load(root, e + Lam));
-          else
-            dst[e] = TR::f(src[e], src[e + Lam]);
+          dst[e] = TR::f(src[e], src[e + Lam]);
         }
       } else {
 #pragma unroll
@@ -80,10 +91,7 @@ __device__ __forceinline__ void big_stages_to(int top, int bottom, int i, uint32
           const uint32_t mlo = readlane(bx, w0), mhi = readlane(bx, w0 + 1);
           const uint32_t m = lane < 32 ? mlo : mhi;
           const bool ub = (m >> (lane & 31)) & 1u;
-          if constexpr (LAM + 1 == LOGN)
-            dst[e] = TR::g(TR::load(root, e), TR::load(root, e + Lam), ub);
-          else
-            dst[e] = TR::g(src[e], src[e + Lam], ub);
+          dst[e] = TR::g(src[e], src[e + Lam], ub);
         }
       }
       if constexpr (STATS) fg += (uint32_t)Lam;
