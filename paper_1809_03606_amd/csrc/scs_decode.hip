@@ -9,9 +9,10 @@
 // Mapping (one wavefront of 64 lanes decodes one frame):
 //   * alpha tree in LDS: stage lambda (Lambda = 2^lambda values) at word offset
 //     Lambda - 1.  Stages with Lambda >= 64 are computed 64 values per instruction (value
-//     e in lane e mod 64); stages with Lambda <= 32 run in one register with the partner
-//     value from lane e xor Lambda (DPP / ds_swizzle / ds_bpermute).  The channel LLRs (stage
-//     n) are read from the input.
+//     e in lane e mod 64; the top two stages, rebuilt from the channel LLRs, give each lane
+//     consecutive values instead); stages with Lambda <= 32 run in one register with the
+//     partner value from lane e xor Lambda (DPP / ds_swizzle / ds_bpermute).  The channel
+//     LLRs (stage n) are read from the input.
 //   * bit vectors (the decided bits of the path in the tree) are one VGPR: lane w holds
 //     bits 32w..32w+31.  The partial sums a g-node needs are the transform of its left
 //     sibling's decided bits, computed when the g-node is evaluated.
