@@ -294,12 +294,15 @@ __device__ __forceinline__ void decode_frame(const CodeArgs& code, const FrameJo
 }
 
 // Wavefronts per SIMD the register allocation must allow: the one-bank kernels fit 7 (at
-// most 72 VGPRs) and are held to it; the deeper banked stacks keep the compiler's choice.
-template <int NB>
-constexpr int scs_waves_per_simd() { return NB == 1 ? 7 : 1; }
+// most 72 VGPRs) and are held to it (the compiler takes 8 where it can); the two-bank
+// kernels up to N = 1024 are held to 8 (64 VGPRs, without spilling), the other banked
+// kernels to 6 (80 VGPRs, a few words spilled): left free, the top stages' loads raised
+// them to 67-105 VGPRs and one or two wavefronts fewer, 1-9 % slower.
+template <int NB, int LOGN>
+constexpr int scs_waves_per_simd() { return NB == 1 ? 7 : NB == 2 && LOGN <= 10 ? 8 : 6; }
 
 template <int LOGN, class TR, bool STATS, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scs_waves_per_simd<NB>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scs_waves_per_simd<NB, LOGN>())))
 void scs_uniform_kernel(CodeArgs code, int D, int L,
                                                           const typename TR::In* __restrict__ llr,
                                                           int64_t n_frames,
