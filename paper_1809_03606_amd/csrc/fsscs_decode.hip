@@ -594,9 +594,13 @@ __device__ __forceinline__ void fsscs_frame(const CodeArgs& code, const FrameJob
 
 // The int8 kernel with one stack bank is held to 72 VGPRs (7 wavefronts per SIMD instead of
 // 5 at the compiler's 84): 6 % faster on PC(1024,512), D = 32.  The same limit slows the
-// binary32 kernels (74 and 77 VGPRs), which keep the compiler's choice.
+// binary32 kernels (74 and 77 VGPRs), which keep the compiler's choice.  The four-bank
+// kernels are held to 80 VGPRs (6 per SIMD instead of 4 at the compiler's 112, a few words
+// spilled): 12 % faster at D = 256.
 template <class TR, int NB>
-constexpr int fsscs_waves_per_simd() { return std::is_same<TR, TrI8>::value && NB == 1 ? 7 : 1; }
+constexpr int fsscs_waves_per_simd() {
+  return std::is_same<TR, TrI8>::value && NB == 1 ? 7 : NB == 4 ? 6 : 1;
+}
 
 template <int LOGN, class TR, bool STATS, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fsscs_waves_per_simd<TR, NB>())))
